@@ -1,0 +1,802 @@
+/*
+ * lbm_oracle.c -- plain FP64 CPU oracle for the lattice Boltzmann stream-collide
+ * path.  TEST INFRASTRUCTURE ONLY: tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load this file; the product library never does.
+ *
+ * What it computes follows the paper's statement of the method (Section 2,
+ * "The Lattice Boltzmann Method", Eq. (1) collision and Eq. (2) streaming),
+ * with the collision operator read as a two-relaxation-time (TRT) operator
+ * (the paper's D3Q19 "Double Relaxation Time" scheme of the LaBS section),
+ * Guo body forcing, halfway bounce-back walls and periodic faces.  The memory
+ * layout is deliberately different from the GPU path: two full lattices and a
+ * push (scatter) streaming step, one loop nest per time step, no fusion
+ * beyond what Eq. (1)-(2) state.
+ *
+ * Everything is FP64.  The optional BF16 switch of the MLP routines emulates
+ * the rounding of operands to bfloat16 (round to nearest even) so that the
+ * GPU inference can be compared at its own precision; accumulation stays FP64.
+ *
+ * Parity status of each function is stated in its comment ("pinned by ...").
+ * Functions without such a pin say "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Velocity sets.  Pairs are (odd, odd+1): direction i and its opposite.     */
+/* D3Q19: rest, 6 face neighbours, 12 edge neighbours.                       */
+/* D3Q27: D3Q19 plus the 8 corner neighbours.                                */
+/* Weights: D3Q19 1/3, 1/18, 1/36.  D3Q27 8/27, 2/27, 1/54, 1/216.           */
+/* Pinned by the exact moment identities of the velocity set (tests).        */
+/* ------------------------------------------------------------------------ */
+static const int VEL[27][3] = {
+    {0, 0, 0},
+    {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},   {0, -1, 0},  {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0},
+    {1, 0, 1},   {-1, 0, -1}, {1, 0, -1},  {-1, 0, 1},
+    {0, 1, 1},   {0, -1, -1}, {0, 1, -1},  {0, -1, 1},
+    {1, 1, 1},   {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1},  {-1, 1, -1}, {-1, 1, 1},  {1, -1, -1},
+};
+
+static double weight(int q, int i)
+{
+    int n = abs(VEL[i][0]) + abs(VEL[i][1]) + abs(VEL[i][2]);
+    if (q == 19) {
+        if (n == 0) return 1.0 / 3.0;
+        if (n == 1) return 1.0 / 18.0;
+        return 1.0 / 36.0;
+    }
+    if (n == 0) return 8.0 / 27.0;
+    if (n == 1) return 2.0 / 27.0;
+    if (n == 2) return 1.0 / 54.0;
+    return 1.0 / 216.0;
+}
+
+static int opposite(int i)
+{
+    if (i == 0) return 0;
+    return (i % 2 == 1) ? i + 1 : i - 1;
+}
+
+/* Copy the velocity set out for the tests: c[q][3], w[q], opp[q]. */
+int orc_velocity_set(int q, int *c, double *w, int *opp)
+{
+    if (q != 19 && q != 27) return -1;
+    for (int i = 0; i < q; ++i) {
+        for (int a = 0; a < 3; ++a) c[3 * i + a] = VEL[i][a];
+        w[i] = weight(q, i);
+        opp[i] = opposite(i);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Equilibrium: second-order polynomial in u on both lattices,              */
+/*   f_i^eq = w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u),  c_s^2 = 1/3.     */
+/* Pinned by its moments rho, rho u, rho/3 I + rho u u (tests).              */
+/* ------------------------------------------------------------------------ */
+void orc_equilibrium(int q, double rho, const double *u, double *feq)
+{
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < q; ++i) {
+        double cu = VEL[i][0] * u[0] + VEL[i][1] * u[1] + VEL[i][2] * u[2];
+        feq[i] = weight(q, i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Guo forcing term S_i = w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)].           */
+/* Pinned through the collision invariants (momentum gains exactly F).      */
+/* ------------------------------------------------------------------------ */
+static void guo_source(int q, const double *u, const double *F, double *S)
+{
+    for (int i = 0; i < q; ++i) {
+        double cu = VEL[i][0] * u[0] + VEL[i][1] * u[1] + VEL[i][2] * u[2];
+        double cF = VEL[i][0] * F[0] + VEL[i][1] * F[1] + VEL[i][2] * F[2];
+        double cmuF = (VEL[i][0] - u[0]) * F[0] + (VEL[i][1] - u[1]) * F[1] + (VEL[i][2] - u[2]) * F[2];
+        S[i] = weight(q, i) * (3.0 * cmuF + 9.0 * cu * cF);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Closure parameters and the MLP (6 -> 32 -> 32 -> 1).                     */
+/* ------------------------------------------------------------------------ */
+enum { CL_NONE = 0, CL_SMAG = 1, CL_MLP = 2 };
+enum { MLP_IN = 6, MLP_H = 32 };
+#define MLP_NPARAM (MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1) /* 1313 */
+#define MLP_NNORM (4 * MLP_IN)                                                 /* mu, sigma, lo, hi */
+
+/* Round a double to the nearest bfloat16 value (ties to even), via float.   */
+/* Pinned against torch's float -> bfloat16 conversion (tests).              */
+double orc_round_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    if ((b & 0x7f800000u) == 0x7f800000u) return (double)f; /* inf / nan */
+    uint32_t lsb = (b >> 16) & 1u;
+    b += 0x7fffu + lsb;
+    b &= 0xffff0000u;
+    memcpy(&f, &b, 4);
+    return (double)f;
+}
+
+static double rnd(double x, int bf16) { return bf16 ? orc_round_bf16(x) : x; }
+
+static double softplus(double o) { return o > 30.0 ? o : log1p(exp(o)); }
+
+/*
+ * MLP forward for one input vector x[6] (already raw features).  Layout of
+ * params: W1[32][6], b1[32], W2[32][32], b2[32], W3[32], b3.  Inputs are
+ * standardised with norm = {mu[6], sigma[6], lo[6], hi[6]}.  Hidden layers
+ * use tanh; the output passes through softplus so the correction is >= 0.
+ * With bf16 != 0, every matrix operand (inputs and weights of each layer)
+ * is rounded to bfloat16 first; sums, biases and activations are FP64.
+ * Returns the relaxation-time correction; h1, h2 (nullable) receive the
+ * hidden activations, o_out the pre-softplus output.
+ * Pinned by finite differences of its backward pass and by closed-form
+ * single-unit cases (tests).
+ */
+double orc_mlp_forward1(const double *params, const double *norm, const double *x, int bf16,
+                        double *h1_out, double *h2_out, double *o_out)
+{
+    const double *W1 = params;
+    const double *b1 = W1 + MLP_H * MLP_IN;
+    const double *W2 = b1 + MLP_H;
+    const double *b2 = W2 + MLP_H * MLP_H;
+    const double *W3 = b2 + MLP_H;
+    const double *b3 = W3 + MLP_H;
+    double z[MLP_IN], h1[MLP_H], h2[MLP_H];
+    for (int k = 0; k < MLP_IN; ++k) z[k] = (x[k] - norm[k]) / norm[MLP_IN + k];
+    for (int j = 0; j < MLP_H; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < MLP_IN; ++k) s += rnd(W1[j * MLP_IN + k], bf16) * rnd(z[k], bf16);
+        h1[j] = tanh(s + b1[j]);
+    }
+    for (int j = 0; j < MLP_H; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < MLP_H; ++k) s += rnd(W2[j * MLP_H + k], bf16) * rnd(h1[k], bf16);
+        h2[j] = tanh(s + b2[j]);
+    }
+    double o = b3[0];
+    {
+        double s = 0.0;
+        for (int k = 0; k < MLP_H; ++k) s += rnd(W3[k], bf16) * rnd(h2[k], bf16);
+        o += s;
+    }
+    if (h1_out) memcpy(h1_out, h1, sizeof h1);
+    if (h2_out) memcpy(h2_out, h2, sizeof h2);
+    if (o_out) *o_out = o;
+    return softplus(o);
+}
+
+/* Batched forward: x[n][6] -> y[n].  Pinned as orc_mlp_forward1. */
+void orc_mlp_forward(const double *params, const double *norm, const double *x, int64_t n, int bf16,
+                     double *y)
+{
+    for (int64_t r = 0; r < n; ++r) y[r] = orc_mlp_forward1(params, norm, x + 6 * r, bf16, 0, 0, 0);
+}
+
+/*
+ * Loss and gradient for a batch: loss = (1/n) sum_r (y_r - t_r)^2 with y the
+ * MLP output.  grad[1313] receives d loss / d params (plain FP64 backward by
+ * the chain rule through softplus, the two tanh layers and the affine maps).
+ * Returns the loss.  Pinned by central finite differences (tests).
+ */
+double orc_mlp_loss_grad(const double *params, const double *norm, const double *x, const double *t,
+                         int64_t n, double *grad)
+{
+    const double *W2 = params + MLP_H * MLP_IN + MLP_H;
+    const double *W3 = W2 + MLP_H * MLP_H + MLP_H;
+    double *gW1 = grad;
+    double *gb1 = gW1 + MLP_H * MLP_IN;
+    double *gW2 = gb1 + MLP_H;
+    double *gb2 = gW2 + MLP_H * MLP_H;
+    double *gW3 = gb2 + MLP_H;
+    double *gb3 = gW3 + MLP_H;
+    memset(grad, 0, sizeof(double) * MLP_NPARAM);
+    double loss = 0.0;
+    for (int64_t r = 0; r < n; ++r) {
+        const double *xr = x + 6 * r;
+        double h1[MLP_H], h2[MLP_H], o, z[MLP_IN];
+        double y = orc_mlp_forward1(params, norm, xr, 0, h1, h2, &o);
+        for (int k = 0; k < MLP_IN; ++k) z[k] = (xr[k] - norm[k]) / norm[MLP_IN + k];
+        double e = y - t[r];
+        loss += e * e;
+        /* d loss_r / d y = 2 e / n ; softplus'(o) = logistic(o) */
+        double dy = 2.0 * e / (double)n;
+        double dout = dy / (1.0 + exp(-o));
+        gb3[0] += dout;
+        double d2[MLP_H];
+        for (int k = 0; k < MLP_H; ++k) {
+            gW3[k] += dout * h2[k];
+            d2[k] = dout * W3[k] * (1.0 - h2[k] * h2[k]);
+        }
+        double d1[MLP_H];
+        for (int k = 0; k < MLP_H; ++k) d1[k] = 0.0;
+        for (int j = 0; j < MLP_H; ++j) {
+            gb2[j] += d2[j];
+            for (int k = 0; k < MLP_H; ++k) {
+                gW2[j * MLP_H + k] += d2[j] * h1[k];
+                d1[k] += d2[j] * W2[j * MLP_H + k];
+            }
+        }
+        for (int k = 0; k < MLP_H; ++k) d1[k] *= (1.0 - h1[k] * h1[k]);
+        for (int j = 0; j < MLP_H; ++j) {
+            gb1[j] += d1[j];
+            for (int k = 0; k < MLP_IN; ++k) gW1[j * MLP_IN + k] += d1[j] * z[k];
+        }
+    }
+    return loss / (double)n;
+}
+
+/*
+ * One Adam update (Kingma & Ba, 2015) of p[n] with gradient g[n] and moment
+ * buffers m[n], v[n]; step is the 1-based update count.
+ * Pinned by the closed form of the first update (|dp| = lr for every
+ * non-zero gradient component) in the tests.
+ */
+void orc_adam(double *p, const double *g, double *m, double *v, int64_t n, int64_t step, double lr,
+              double beta1, double beta2, double eps)
+{
+    double c1 = 1.0 - pow(beta1, (double)step);
+    double c2 = 1.0 - pow(beta2, (double)step);
+    for (int64_t k = 0; k < n; ++k) {
+        m[k] = beta1 * m[k] + (1.0 - beta1) * g[k];
+        v[k] = beta2 * v[k] + (1.0 - beta2) * g[k] * g[k];
+        double mh = m[k] / c1, vh = v[k] / c2;
+        p[k] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Smagorinsky closure in the Hou et al. (1996) form.                        */
+/* tau_tot solves tau_tot^2 - tau tau_tot - (9 sqrt2 / 2) Cs^2 Q / rho = 0,  */
+/* Q = |P_c| (Frobenius norm of the non-equilibrium momentum flux).          */
+/* Pinned by the residual of that quadratic and by Cs = 0 -> tau (tests).    */
+/* ------------------------------------------------------------------------ */
+double orc_smagorinsky_tau(double tau, double cs, double Q, double rho)
+{
+    return 0.5 * (tau + sqrt(tau * tau + 18.0 * sqrt(2.0) * cs * cs * Q / rho));
+}
+
+/*
+ * The six local features of a cell given its non-equilibrium flux per unit
+ * density P (symmetric 3x3, packed xx, yy, zz, xy, xz, yz), its density and
+ * the molecular tau:
+ *   x1 = tr P,  x2 = |P_dev|_F,  x3 = cbrt(det P_dev),  x4 = rho - 1,
+ *   x5 = tau_smag - tau (Cs of the domain, Q = rho |P|),  x6 = tau.
+ * Pinned by invariance under rotations and closed forms for diagonal P
+ * (tests).
+ */
+void orc_features(const double *P, double rho, double tau, double cs, double *xo)
+{
+    double tr = P[0] + P[1] + P[2];
+    double d0 = P[0] - tr / 3.0, d1 = P[1] - tr / 3.0, d2 = P[2] - tr / 3.0;
+    double xy = P[3], xz = P[4], yz = P[5];
+    double nd = sqrt(d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * (xy * xy + xz * xz + yz * yz));
+    double det = d0 * (d1 * d2 - yz * yz) - xy * (xy * d2 - yz * xz) + xz * (xy * yz - d1 * xz);
+    double np = sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + 2.0 * (xy * xy + xz * xz + yz * yz));
+    xo[0] = tr;
+    xo[1] = nd;
+    xo[2] = cbrt(det);
+    xo[3] = rho - 1.0;
+    xo[4] = orc_smagorinsky_tau(tau, cs, rho * np, rho) - tau;
+    xo[5] = tau;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Simulation state.                                                         */
+/* ------------------------------------------------------------------------ */
+enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
+
+typedef struct {
+    int q, nx, ny, nz;
+    int64_t n;
+    int bc[6];
+    double ubc[6][3];
+    double rhobc[6];
+    double tau, magic, F[3];
+    int closure;
+    double cs;
+    double mlp[MLP_NPARAM];
+    double norm[MLP_NNORM];
+    unsigned char *solid; /* NULL: all fluid */
+    double *f, *g;        /* [q][n] canonical (post-stream, pre-collide) and scratch */
+    int64_t fallbacks;    /* cells where the MLP closure fell back to Smagorinsky */
+} orc_sim;
+
+static int64_t cell_index(const orc_sim *s, int x, int y, int z)
+{
+    return ((int64_t)z * s->ny + y) * s->nx + x;
+}
+
+static int is_solid(const orc_sim *s, int64_t c) { return s->solid ? s->solid[c] != 0 : 0; }
+
+/*
+ * Create a simulation.  bc[6] for faces -x,+x,-y,+y,-z,+z; ubc[6][3] wall
+ * velocities of velocity faces; rhobc[6] wall densities of velocity and
+ * pressure faces; solid (nullable) one byte per cell, non-zero = solid.
+ * Returns NULL on invalid arguments.
+ */
+orc_sim *orc_create(int q, int nx, int ny, int nz, const int *bc, const double *ubc, const double *rhobc,
+                    const unsigned char *solid, double tau, double magic, const double *F, int closure,
+                    double cs)
+{
+    if ((q != 19 && q != 27) || nx <= 0 || ny <= 0 || nz <= 0 || tau <= 0.5) return NULL;
+    for (int a = 0; a < 3; ++a)
+        if ((bc[2 * a] == BC_PERIODIC) != (bc[2 * a + 1] == BC_PERIODIC)) return NULL;
+    orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+    s->q = q;
+    s->nx = nx;
+    s->ny = ny;
+    s->nz = nz;
+    s->n = (int64_t)nx * ny * nz;
+    for (int k = 0; k < 6; ++k) {
+        s->bc[k] = bc[k];
+        for (int a = 0; a < 3; ++a) s->ubc[k][a] = ubc ? ubc[3 * k + a] : 0.0;
+        s->rhobc[k] = rhobc ? rhobc[k] : 1.0;
+    }
+    s->tau = tau;
+    s->magic = magic;
+    for (int a = 0; a < 3; ++a) s->F[a] = F ? F[a] : 0.0;
+    s->closure = closure;
+    s->cs = cs;
+    if (solid) {
+        s->solid = (unsigned char *)malloc((size_t)s->n);
+        memcpy(s->solid, solid, (size_t)s->n);
+    }
+    s->f = (double *)calloc((size_t)(q * s->n), sizeof(double));
+    s->g = (double *)calloc((size_t)(q * s->n), sizeof(double));
+    return s;
+}
+
+void orc_destroy(orc_sim *s)
+{
+    if (!s) return;
+    free(s->solid);
+    free(s->f);
+    free(s->g);
+    free(s);
+}
+
+void orc_set_mlp(orc_sim *s, const double *params, const double *norm)
+{
+    memcpy(s->mlp, params, sizeof(s->mlp));
+    memcpy(s->norm, norm, sizeof(s->norm));
+}
+
+int64_t orc_fallbacks(const orc_sim *s) { return s->fallbacks; }
+
+/* Set the state to f^eq(rho, u) at every fluid cell; u is [3][n].  Solid   */
+/* cells hold zeros.                                                         */
+void orc_init_equilibrium(orc_sim *s, const double *rho, const double *u)
+{
+    double feq[27], uc[3];
+    for (int64_t c = 0; c < s->n; ++c) {
+        for (int a = 0; a < 3; ++a) uc[a] = u[a * s->n + c];
+        orc_equilibrium(s->q, rho[c], uc, feq);
+        for (int i = 0; i < s->q; ++i) s->f[i * s->n + c] = is_solid(s, c) ? 0.0 : feq[i];
+    }
+}
+
+void orc_set_pdfs(orc_sim *s, const double *f) { memcpy(s->f, f, sizeof(double) * s->q * s->n); }
+void orc_get_pdfs(const orc_sim *s, double *f) { memcpy(f, s->f, sizeof(double) * s->q * s->n); }
+
+/*
+ * Collide one cell: f[q] in, fstar[q] out; u_out receives the cell velocity
+ * u = (j + F/2) / rho; tau_out the relaxation time used.  This is Eq. (1)
+ * with the relaxation split over the symmetric and antisymmetric parts of
+ * each pair (i, opposite(i)):
+ *   f*_i = f_i - w+ (f+_i - eq+_i) - w- (f-_i - eq-_i) + (1 - w+/2) S+_i + (1 - w-/2) S-_i
+ * with w+ = 1/tau and w- = 1 / (1/2 + magic / (tau - 1/2)).
+ * Pinned by: mass and momentum invariants, the BGK special case, the exact
+ * Poiseuille profile and the Taylor-Green decay rate (tests).
+ */
+static void collide_cell(const orc_sim *s, const double *f, double *fstar, double *u_out, double *tau_out,
+                         int64_t *fallback)
+{
+    int q = s->q;
+    double rho = 0.0, j[3] = {0, 0, 0};
+    for (int i = 0; i < q; ++i) {
+        rho += f[i];
+        for (int a = 0; a < 3; ++a) j[a] += VEL[i][a] * f[i];
+    }
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * s->F[a]) / rho;
+    double feq[27], S[27];
+    orc_equilibrium(q, rho, u, feq);
+    guo_source(q, u, s->F, S);
+
+    double tau = s->tau;
+    if (s->closure != CL_NONE) {
+        /* Non-equilibrium momentum flux with the forcing correction:        */
+        /* P_c = sum_i c_i c_i (f_i - feq_i) + (u F + F u) / 2                */
+        double Pc[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double acc = 0.0;
+                for (int i = 0; i < q; ++i) acc += VEL[i][a] * VEL[i][b] * (f[i] - feq[i]);
+                Pc[a][b] = acc + 0.5 * (u[a] * s->F[b] + s->F[a] * u[b]);
+            }
+        double Q = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Q += Pc[a][b] * Pc[a][b];
+        Q = sqrt(Q);
+        double tau_smag = orc_smagorinsky_tau(s->tau, s->cs, Q, rho);
+        if (s->closure == CL_SMAG) {
+            tau = tau_smag;
+        } else {
+            double P[6] = {Pc[0][0] / rho, Pc[1][1] / rho, Pc[2][2] / rho,
+                           Pc[0][1] / rho, Pc[0][2] / rho, Pc[1][2] / rho};
+            double x[6];
+            orc_features(P, rho, s->tau, s->cs, x);
+            int inside = 1;
+            for (int k = 0; k < 6; ++k)
+                if (!(x[k] >= s->norm[2 * MLP_IN + k] && x[k] <= s->norm[3 * MLP_IN + k])) inside = 0;
+            double dt = inside ? orc_mlp_forward1(s->mlp, s->norm, x, 1, 0, 0, 0) : NAN;
+            if (inside && isfinite(dt)) {
+                tau = s->tau + dt;
+            } else {
+                tau = tau_smag;
+                if (fallback) ++*fallback;
+            }
+        }
+    }
+    double wp = 1.0 / tau;
+    double wm = 1.0 / (0.5 + s->magic / (tau - 0.5));
+    for (int i = 0; i < q; ++i) {
+        int ib = opposite(i);
+        double fp = 0.5 * (f[i] + f[ib]), fm = 0.5 * (f[i] - f[ib]);
+        double ep = 0.5 * (feq[i] + feq[ib]), em = 0.5 * (feq[i] - feq[ib]);
+        double sp = 0.5 * (S[i] + S[ib]), sm = 0.5 * (S[i] - S[ib]);
+        fstar[i] = f[i] - wp * (fp - ep) - wm * (fm - em) + (1.0 - 0.5 * wp) * sp + (1.0 - 0.5 * wm) * sm;
+    }
+    if (u_out)
+        for (int a = 0; a < 3; ++a) u_out[a] = u[a];
+    if (tau_out) *tau_out = tau;
+}
+
+/* Collide a single cell without a simulation (for the invariant tests).    */
+void orc_collide(int q, const double *f, double tau, double magic, const double *F, int closure, double cs,
+                 double *fstar, double *tau_used)
+{
+    orc_sim s;
+    memset(&s, 0, sizeof s);
+    s.q = q;
+    s.tau = tau;
+    s.magic = magic;
+    for (int a = 0; a < 3; ++a) s.F[a] = F[a];
+    s.closure = closure;
+    s.cs = cs;
+    collide_cell(&s, f, fstar, 0, tau_used, 0);
+}
+
+/* Non-equilibrium flux of one cell, packed xx,yy,zz,xy,xz,yz (for tests). */
+void orc_noneq_flux(int q, const double *f, const double *F, double *P6)
+{
+    double rho = 0.0, j[3] = {0, 0, 0};
+    for (int i = 0; i < q; ++i) {
+        rho += f[i];
+        for (int a = 0; a < 3; ++a) j[a] += VEL[i][a] * f[i];
+    }
+    double u[3], feq[27];
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * F[a]) / rho;
+    orc_equilibrium(q, rho, u, feq);
+    static const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+    for (int k = 0; k < 6; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < q; ++i) acc += VEL[i][A[k]] * VEL[i][B[k]] * (f[i] - feq[i]);
+        P6[k] = acc + 0.5 * (u[A[k]] * F[B[k]] + F[A[k]] * u[B[k]]);
+    }
+}
+
+/*
+ * Streaming of one post-collision population, Eq. (2), in push form: the
+ * value v leaving cell (x,y,z) along c_i lands at the neighbour, or, when the
+ * link is cut by a wall, returns to the same cell in the opposite direction:
+ *   solid neighbour or no-slip face:  g_opp(i)(x) = v
+ *   velocity face (u_w, rho_w):      g_opp(i)(x) = v - 6 w_i rho_w (c_i . u_w)
+ *   pressure face (rho_w):           g_opp(i)(x) = -v + 2 w_i rho_w (1 + 9/2 (c_i.u)^2 - 3/2 u.u)
+ * (u = this cell's velocity).  A link leaving through several non-periodic
+ * faces takes the first of no-slip, velocity, pressure (lowest face index
+ * among equals).  Periodic faces wrap.
+ * The target cell and slot are returned through tgt/dir.
+ */
+static double push_target(const orc_sim *s, int x, int y, int z, int i, double v, const double *u, int64_t *tgt,
+                          int *dir)
+{
+    int p[3] = {x + VEL[i][0], y + VEL[i][1], z + VEL[i][2]};
+    int ext[3] = {s->nx, s->ny, s->nz};
+    int cut_kind = -1, cut_face = -1;
+    static const int rank_of[4] = {0, 3, 2, 1}; /* precedence: no-slip > velocity > pressure */
+    for (int a = 0; a < 3; ++a) {
+        int face = -1;
+        if (p[a] < 0) face = 2 * a;
+        if (p[a] >= ext[a]) face = 2 * a + 1;
+        if (face < 0) continue;
+        if (s->bc[face] == BC_PERIODIC) {
+            p[a] = (p[a] + ext[a]) % ext[a];
+        } else if (cut_kind < 0 || rank_of[s->bc[face]] > rank_of[cut_kind]) {
+            cut_kind = s->bc[face];
+            cut_face = face;
+        }
+    }
+    int64_t self = cell_index(s, x, y, z);
+    if (cut_kind < 0) {
+        int64_t c = cell_index(s, p[0], p[1], p[2]);
+        if (!is_solid(s, c)) {
+            *tgt = c;
+            *dir = i;
+            return v;
+        }
+        cut_kind = BC_NOSLIP;
+    }
+    *tgt = self;
+    *dir = opposite(i);
+    double w = weight(s->q, i);
+    if (cut_kind == BC_NOSLIP) return v;
+    if (cut_kind == BC_VELOCITY) {
+        const double *uw = s->ubc[cut_face];
+        double cuw = VEL[i][0] * uw[0] + VEL[i][1] * uw[1] + VEL[i][2] * uw[2];
+        return v - 6.0 * w * s->rhobc[cut_face] * cuw;
+    }
+    double cu = VEL[i][0] * u[0] + VEL[i][1] * u[1] + VEL[i][2] * u[2];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return -v + 2.0 * w * s->rhobc[cut_face] * (1.0 + 4.5 * cu * cu - 1.5 * uu);
+}
+
+/*
+ * Advance n time steps: for every fluid cell collide (Eq. 1) and push every
+ * population to its destination (Eq. 2) in a second lattice, then swap.
+ * Pinned by Poiseuille, Taylor-Green, conservation, symmetry and plug-flow
+ * tests.
+ */
+void orc_step(orc_sim *s, int64_t nsteps)
+{
+    int q = s->q;
+    int64_t N = s->n;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        int64_t fb = 0;
+#pragma omp parallel for schedule(static) reduction(+ : fb)
+        for (int z = 0; z < s->nz; ++z)
+            for (int y = 0; y < s->ny; ++y)
+                for (int x = 0; x < s->nx; ++x) {
+                    int64_t c = cell_index(s, x, y, z);
+                    if (is_solid(s, c)) continue;
+                    double f[27], fs[27], u[3];
+                    for (int i = 0; i < q; ++i) f[i] = s->f[i * N + c];
+                    collide_cell(s, f, fs, u, 0, &fb);
+                    for (int i = 0; i < q; ++i) {
+                        int64_t tgt;
+                        int d;
+                        double v = push_target(s, x, y, z, i, fs[i], u, &tgt, &d);
+                        s->g[d * N + tgt] = v;
+                    }
+                }
+        s->fallbacks += fb;
+        double *tmp = s->f;
+        s->f = s->g;
+        s->g = tmp;
+    }
+}
+
+/* Density and velocity u = (j + F/2)/rho of the canonical state; u [3][n]. */
+void orc_moments(const orc_sim *s, double *rho, double *u)
+{
+    int64_t N = s->n;
+    for (int64_t c = 0; c < N; ++c) {
+        double r = 0.0, j[3] = {0, 0, 0};
+        for (int i = 0; i < s->q; ++i) {
+            double v = s->f[i * N + c];
+            r += v;
+            for (int a = 0; a < 3; ++a) j[a] += VEL[i][a] * v;
+        }
+        rho[c] = r;
+        for (int a = 0; a < 3; ++a) u[a * N + c] = is_solid(s, c) ? 0.0 : (j[a] + 0.5 * s->F[a]) / r;
+    }
+}
+
+/* Totals over fluid cells: mass = sum rho, mom = sum j (raw first moment). */
+void orc_totals(const orc_sim *s, double *mass, double *mom)
+{
+    int64_t N = s->n;
+    double m = 0.0, p[3] = {0, 0, 0};
+    for (int64_t c = 0; c < N; ++c) {
+        if (is_solid(s, c)) continue;
+        for (int i = 0; i < s->q; ++i) {
+            double v = s->f[i * N + c];
+            m += v;
+            for (int a = 0; a < 3; ++a) p[a] += VEL[i][a] * v;
+        }
+    }
+    *mass = m;
+    for (int a = 0; a < 3; ++a) mom[a] = p[a];
+}
+
+/*
+ * Probe: canonical populations at selected cells after k steps, starting
+ * from f^eq(rho, u) of the given fields (t = 0), without storing a lattice.
+ * Each value at (y, i, t+1) is the single push of Eq. (2) that lands there:
+ * from y - c_i when that cell is a fluid cell reached without crossing a
+ * non-periodic face, else from y itself in direction opposite(i) (the cut
+ * link).  Recursion depth k; cost grows as Q^k per probed cell, so keep k
+ * small (1..3).  out[ncell][q].
+ * Pinned against orc_step on small domains (tests).
+ */
+static void probe_rec(const orc_sim *s, const double *rho, const double *u, int x, int y, int z, int k,
+                      double *f_out);
+
+static void probe_post(const orc_sim *s, const double *rho, const double *u, int x, int y, int z, int k,
+                       double *fs, double *uc)
+{
+    double f[27];
+    probe_rec(s, rho, u, x, y, z, k, f);
+    collide_cell(s, f, fs, uc, 0, 0);
+}
+
+static void probe_rec(const orc_sim *s, const double *rho, const double *u, int x, int y, int z, int k,
+                      double *f_out)
+{
+    int64_t c = cell_index(s, x, y, z);
+    if (k == 0) {
+        double uc[3] = {u[c], u[s->n + c], u[2 * s->n + c]};
+        orc_equilibrium(s->q, rho[c], uc, f_out);
+        return;
+    }
+    int ext[3] = {s->nx, s->ny, s->nz};
+    for (int i = 0; i < s->q; ++i) {
+        int p[3] = {x - VEL[i][0], y - VEL[i][1], z - VEL[i][2]};
+        int crossed = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (p[a] >= 0 && p[a] < ext[a]) continue;
+            int face = p[a] < 0 ? 2 * a : 2 * a + 1;
+            if (s->bc[face] == BC_PERIODIC)
+                p[a] = (p[a] + ext[a]) % ext[a];
+            else
+                crossed = 1;
+        }
+        int64_t tgt;
+        int d;
+        double fs[27], uc[3], v;
+        if (!crossed && !is_solid(s, cell_index(s, p[0], p[1], p[2]))) {
+            probe_post(s, rho, u, p[0], p[1], p[2], k - 1, fs, uc);
+            v = push_target(s, p[0], p[1], p[2], i, fs[i], uc, &tgt, &d);
+        } else {
+            probe_post(s, rho, u, x, y, z, k - 1, fs, uc);
+            v = push_target(s, x, y, z, opposite(i), fs[opposite(i)], uc, &tgt, &d);
+        }
+        f_out[i] = (tgt == c && d == i) ? v : NAN;
+    }
+}
+
+void orc_probe(const orc_sim *s, const double *rho, const double *u, int k, int64_t ncell, const int64_t *cells,
+               double *out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t r = 0; r < ncell; ++r) {
+        int64_t c = cells[r];
+        int x = (int)(c % s->nx);
+        int y = (int)((c / s->nx) % s->ny);
+        int z = (int)(c / ((int64_t)s->nx * s->ny));
+        probe_rec(s, rho, u, x, y, z, k, out + r * s->q);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Training-data builders for the learned closure.                           */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Box filter: average fine fields over non-overlapping 4x4x4 blocks.
+ * rho[nf], u[3][nf] in; out[10][nc] = rho, u_x, u_y, u_z, then the filtered
+ * products uu in the order xx, yy, zz, xy, xz, yz.  Fine dims must be
+ * multiples of 4.  Pinned by: constants map to constants, block sums are
+ * preserved, a linear field maps to its block-centre value (tests).
+ */
+void orc_box_filter4(int nx, int ny, int nz, const double *rho, const double *u, double *out)
+{
+    int cx = nx / 4, cy = ny / 4, cz = nz / 4;
+    int64_t nf = (int64_t)nx * ny * nz, nc = (int64_t)cx * cy * cz;
+    static const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+    for (int64_t k = 0; k < 10 * nc; ++k) out[k] = 0.0;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                int64_t f = ((int64_t)z * ny + y) * nx + x;
+                int64_t c = ((int64_t)(z / 4) * cy + y / 4) * cx + x / 4;
+                out[c] += rho[f] / 64.0;
+                for (int a = 0; a < 3; ++a) out[(1 + a) * nc + c] += u[a * nf + f] / 64.0;
+                for (int m = 0; m < 6; ++m) out[(4 + m) * nc + c] += u[A[m] * nf + f] * u[B[m] * nf + f] / 64.0;
+            }
+}
+
+/*
+ * Derivative of a cell-centred field g along axis a at cell index i (0..n-1):
+ * central difference inside; on a periodic axis the stencil wraps; next to a
+ * wall face (non-periodic axis, wall halfway outside the first/last cell,
+ * value zero there) the derivative of the quadratic through the wall point
+ * and the two nearest cells: d = g0 + g1/3 at the low wall, mirrored at the
+ * high wall.  Pinned by exactness on quadratics (tests).
+ */
+static double deriv(const double *g, int64_t stride, int i, int n, int periodic)
+{
+    if (periodic) {
+        int im = (i - 1 + n) % n, ip = (i + 1) % n;
+        return 0.5 * (g[(int64_t)ip * stride] - g[(int64_t)im * stride]);
+    }
+    if (n == 1) return 0.0;
+    if (i == 0) return g[0] + g[stride] / 3.0;
+    if (i == n - 1) return -(g[(int64_t)(n - 1) * stride] + g[(int64_t)(n - 2) * stride] / 3.0);
+    return 0.5 * (g[(int64_t)(i + 1) * stride] - g[(int64_t)(i - 1) * stride]);
+}
+
+/* Filtered strain rate S (packed xx,yy,zz,xy,xz,yz) of the coarse field u. */
+void orc_strain(int cx, int cy, int cz, const int *periodic, const double *u, double *S)
+{
+    int64_t nc = (int64_t)cx * cy * cz;
+    int ext[3] = {cx, cy, cz};
+    int64_t strd[3] = {1, cx, (int64_t)cx * cy};
+    for (int z = 0; z < cz; ++z)
+        for (int y = 0; y < cy; ++y)
+            for (int x = 0; x < cx; ++x) {
+                int64_t c = ((int64_t)z * cy + y) * cx + x;
+                int pos[3] = {x, y, z};
+                double G[3][3]; /* G[a][b] = d u_a / d x_b */
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        const double *base = u + a * nc + c - (int64_t)pos[b] * strd[b];
+                        G[a][b] = deriv(base, strd[b], pos[b], ext[b], periodic[b]);
+                    }
+                S[0 * nc + c] = G[0][0];
+                S[1 * nc + c] = G[1][1];
+                S[2 * nc + c] = G[2][2];
+                S[3 * nc + c] = 0.5 * (G[0][1] + G[1][0]);
+                S[4 * nc + c] = 0.5 * (G[0][2] + G[2][0]);
+                S[5 * nc + c] = 0.5 * (G[1][2] + G[2][1]);
+            }
+}
+
+/*
+ * Closure dataset from box-filtered fields filt[10][nc] (as produced by
+ * orc_box_filter4): per coarse cell the target dtau* = 3 nu_t* with
+ *   tau_sgs = <u u> - <u><u>,  nu_t* = max(0, -dev(tau_sgs):S / (2 S:S + eps)),
+ * and the six features of the flux the coarse lattice would carry,
+ * P = -(2/3)(tau + dtau*) S.  x[nc][6], t[nc].
+ * Parity unpinned beyond its parts (strain, features) and the closed form of
+ * a pure-shear sample (tests).
+ */
+void orc_closure_dataset(int cx, int cy, int cz, const int *periodic, const double *filt, double tau, double cs,
+                         double eps, double *x, double *t)
+{
+    int64_t nc = (int64_t)cx * cy * cz;
+    double *S = (double *)malloc(sizeof(double) * 6 * nc);
+    orc_strain(cx, cy, cz, periodic, filt + nc, S);
+    static const int A[6] = {0, 1, 2, 0, 0, 1}, B[6] = {0, 1, 2, 1, 2, 2};
+    for (int64_t c = 0; c < nc; ++c) {
+        double ts[6], Sc[6];
+        for (int m = 0; m < 6; ++m) {
+            ts[m] = filt[(4 + m) * nc + c] - filt[(1 + A[m]) * nc + c] * filt[(1 + B[m]) * nc + c];
+            Sc[m] = S[m * nc + c];
+        }
+        double trt = (ts[0] + ts[1] + ts[2]) / 3.0;
+        double dd = 0.0, ss = 0.0;
+        for (int m = 0; m < 6; ++m) {
+            double mult = m < 3 ? 1.0 : 2.0;
+            double tdev = m < 3 ? ts[m] - trt : ts[m];
+            dd += mult * tdev * Sc[m];
+            ss += mult * Sc[m] * Sc[m];
+        }
+        double nut = -dd / (2.0 * ss + eps);
+        if (nut < 0.0) nut = 0.0;
+        double dtau = 3.0 * nut;
+        double P[6];
+        for (int m = 0; m < 6; ++m) P[m] = -(2.0 / 3.0) * (tau + dtau) * Sc[m];
+        orc_features(P, filt[c], tau, cs, x + 6 * c);
+        t[c] = dtau;
+    }
+    free(S);
+}

@@ -1,0 +1,117 @@
+"""Seeded synthetic inputs: macroscopic initial fields and solid masks.
+
+This module holds no lattice Boltzmann arithmetic: it produces density and
+velocity fields (FP64, [nz, ny, nx] and [3, nz, ny, nx], x fastest) and solid
+masks from closed-form flow fields and a seeded PCG64 generator.  Both the
+oracle and the GPU path build their own initial populations from these
+fields.
+
+Workloads (the paper's own channel and landing-gear geometries are not
+available, so these stand in for them with the stated shapes):
+  * Taylor-Green vortex: the 2-D mode in x-y, uniform in z.
+  * Channel: walls on the y faces (halfway between the first/last row and the
+    face), laminar parabola plus uniform noise, periodic in x and z -- the
+    shape of the paper's turbulent-channel benchmark.
+  * Obstacles: random non-overlapping solid spheres filling a volume
+    fraction -- a stand-in for the landing-gear geometry.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def taylor_green(nx: int, ny: int, nz: int, u0: float = 0.05):
+    """2-D Taylor-Green vortex, k = 2 pi / nx along x and 2 pi / ny along y.
+
+    u = u0 cos(kx x) sin(ky y), v = -u0 sin(kx x) cos(ky y), w = 0, and the
+    matching pressure field expressed as density with c_s^2 = 1/3:
+    rho = 1 - (3 u0^2 / 4) (cos 2 kx x + cos 2 ky y).
+    """
+    kx, ky = 2 * math.pi / nx, 2 * math.pi / ny
+    x = np.arange(nx)[None, None, :]
+    y = np.arange(ny)[None, :, None]
+    shape = (nz, ny, nx)
+    u = np.zeros((3,) + shape)
+    u[0] = np.broadcast_to(u0 * np.cos(kx * x) * np.sin(ky * y), shape)
+    u[1] = np.broadcast_to(-u0 * np.sin(kx * x) * np.cos(ky * y), shape)
+    rho = np.broadcast_to(1.0 - 0.75 * u0 * u0 * (np.cos(2 * kx * x) + np.cos(2 * ky * y)), shape).copy()
+    return rho, u
+
+
+def channel(nx: int, ny: int, nz: int, u_c: float = 0.05, noise: float = 0.05, seed: int = 1234):
+    """Channel with walls half a cell outside rows 0 and ny-1.
+
+    u_x = 4 u_c (y + 1/2)(ny - 1/2 - y) / ny^2 plus i.i.d. uniform noise in
+    [-noise u_c, noise u_c] on every component of every cell, drawn from
+    numpy's PCG64(seed) in C order (z, y, x, component); rho = 1.
+    """
+    y = np.arange(ny, dtype=np.float64)
+    prof = 4.0 * u_c * (y + 0.5) * (ny - 0.5 - y) / (ny * ny)
+    shape = (nz, ny, nx)
+    u = np.zeros((3,) + shape)
+    u[0] = prof[None, :, None]
+    if noise > 0.0:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        amp = noise * u_c
+        n = rng.uniform(-amp, amp, size=shape + (3,))
+        u += np.moveaxis(n, -1, 0)
+    rho = np.ones(shape)
+    return rho, u
+
+
+def spheres(nx: int, ny: int, nz: int, fill: float = 0.10, rmin: float = 6.0, rmax: float = 20.0,
+            x_margin: int = 32, seed: int = 2024, max_tries: int = 200000):
+    """Random non-overlapping solid spheres; returns (mask uint8 [nz,ny,nx], list of (xc,yc,zc,r)).
+
+    Radii are uniform reals in [rmin, rmax]; centres are uniform with
+    x in [x_margin + r, nx - 1 - x_margin - r] and y, z in [r, n - 1 - r]
+    (no periodic wrap).  A candidate is accepted when its centre lies at
+    least r1 + r2 + 1 from every accepted centre.  Spheres are added until
+    the solid voxel fraction reaches `fill`.  A cell (i, j, k) is solid iff
+    (i - xc)^2 + (j - yc)^2 + (k - zc)^2 <= r^2.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    acc = []
+    total = nx * ny * nz
+    solid = 0
+    tries = 0
+    while solid < fill * total:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("spheres: could not reach the requested fill fraction")
+        r = rng.uniform(rmin, rmax)
+        lo_x, hi_x = x_margin + r, nx - 1 - x_margin - r
+        if hi_x < lo_x or ny - 1 - r < r or nz - 1 - r < r:
+            raise ValueError("spheres: domain too small for the radius range")
+        xc = rng.uniform(lo_x, hi_x)
+        yc = rng.uniform(r, ny - 1 - r)
+        zc = rng.uniform(r, nz - 1 - r)
+        if any((xc - a) ** 2 + (yc - b) ** 2 + (zc - c) ** 2 < (r + s + 1.0) ** 2 for a, b, c, s in acc):
+            continue
+        acc.append((xc, yc, zc, r))
+        x0, x1 = max(0, int(math.floor(xc - r))), min(nx - 1, int(math.ceil(xc + r)))
+        y0, y1 = max(0, int(math.floor(yc - r))), min(ny - 1, int(math.ceil(yc + r)))
+        z0, z1 = max(0, int(math.floor(zc - r))), min(nz - 1, int(math.ceil(zc + r)))
+        zz, yy, xx = np.meshgrid(np.arange(z0, z1 + 1), np.arange(y0, y1 + 1), np.arange(x0, x1 + 1), indexing="ij")
+        inside = (xx - xc) ** 2 + (yy - yc) ** 2 + (zz - zc) ** 2 <= r * r
+        sub = mask[z0:z1 + 1, y0:y1 + 1, x0:x1 + 1]
+        solid += int(np.count_nonzero(inside & (sub == 0)))
+        sub[inside] = 1
+    return mask, acc
+
+
+def uniform_flow(nx: int, ny: int, nz: int, u=(0.04, 0.0, 0.0), rho: float = 1.0):
+    shape = (nz, ny, nx)
+    uu = np.zeros((3,) + shape)
+    for a in range(3):
+        uu[a] = u[a]
+    return np.full(shape, float(rho)), uu
+
+
+def perturbation(shape, scale: float, seed: int):
+    """Seeded i.i.d. uniform numbers in [-scale, scale] of the given shape."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-scale, scale, size=shape)

@@ -1,0 +1,593 @@
+"""Pins of the FP64 oracle against facts fixed by the mathematics of the method.
+
+Every test here runs on the CPU.  None of them re-types an oracle formula and
+compares it with itself: they check exact identities of the velocity sets,
+moments, invariants, special cases that reduce to textbook forms (BGK),
+closed-form flows (force-driven Poiseuille, Taylor-Green decay, uniform
+plug flow), symmetries and conservation laws.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import BC_NOSLIP, BC_PERIODIC, BC_PRESSURE, BC_VELOCITY
+from paper_2305_09910_amd import inputs
+
+MAGIC = 3.0 / 16.0
+QS = (19, 27)
+
+
+# --------------------------------------------------------------------------
+# velocity sets and equilibrium
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("q", QS)
+def test_velocity_set_exact_moments(q):
+    c, w, opp = oracle.velocity_set(q)
+    den = 36 if q == 19 else 216
+    wi = np.rint(w * den).astype(np.int64)
+    assert np.allclose(wi / den, w, rtol=0, atol=1e-16)
+    W = [Fraction(int(k), den) for k in wi]
+    assert sum(W) == 1
+    assert len({tuple(v) for v in c}) == q
+    for a in range(3):
+        assert sum(W[i] * c[i, a] for i in range(q)) == 0
+        for b in range(3):
+            m2 = sum(W[i] * c[i, a] * c[i, b] for i in range(q))
+            assert m2 == (Fraction(1, 3) if a == b else 0)
+            for g in range(3):
+                assert sum(W[i] * c[i, a] * c[i, b] * c[i, g] for i in range(q)) == 0
+                for d in range(3):
+                    m4 = sum(W[i] * c[i, a] * c[i, b] * c[i, g] * c[i, d] for i in range(q))
+                    iso = Fraction(1, 9) * ((a == b) * (g == d) + (a == g) * (b == d) + (a == d) * (b == g))
+                    assert m4 == iso
+    # opposite pairs are (odd, odd+1) and really opposite
+    assert opp[0] == 0
+    for i in range(1, q):
+        assert (c[opp[i]] == -c[i]).all()
+        assert opp[i] == (i + 1 if i % 2 else i - 1)
+
+
+@pytest.mark.parametrize("q", QS)
+def test_equilibrium_moments(q):
+    c, w, _ = oracle.velocity_set(q)
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        rho = 1 + rng.uniform(-0.1, 0.1)
+        u = rng.uniform(-0.1, 0.1, 3)
+        feq = oracle.equilibrium(q, rho, u)
+        assert abs(feq.sum() - rho) < 1e-15
+        assert np.allclose(c.T @ feq, rho * u, atol=1e-16)
+        Pi = np.einsum("ia,ib,i->ab", c, c, feq)
+        assert np.allclose(Pi, rho / 3 * np.eye(3) + rho * np.outer(u, u), atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# collision
+# --------------------------------------------------------------------------
+def _random_cell(q, rng, amp=0.01):
+    rho = 1 + rng.uniform(-0.05, 0.05)
+    u = rng.uniform(-0.08, 0.08, 3)
+    feq = oracle.equilibrium(q, rho, u)
+    return feq * (1 + rng.uniform(-amp, amp, q))
+
+
+@pytest.mark.parametrize("q", QS)
+def test_collision_invariants(q):
+    """Mass is unchanged; momentum gains exactly the body force F."""
+    c, w, _ = oracle.velocity_set(q)
+    rng = np.random.default_rng(2)
+    for tau in (0.51, 0.6, 1.0, 1.7):
+        for _ in range(10):
+            f = _random_cell(q, rng)
+            F = rng.uniform(-1e-3, 1e-3, 3)
+            fs, _ = oracle.collide(q, f, tau, MAGIC, F)
+            assert abs(fs.sum() - f.sum()) < 1e-15
+            assert np.allclose(c.T @ fs, c.T @ f + F, rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("q", QS)
+def test_trt_reduces_to_bgk(q):
+    """With magic = (tau - 1/2)^2 both rates coincide and TRT is BGK with Guo's
+    forcing, f* = f - (f - f_eq)/tau + (1 - 1/(2 tau)) S; at tau = 1 this is
+    f_eq + S/2."""
+    c, w, _ = oracle.velocity_set(q)
+    rng = np.random.default_rng(3)
+    for tau in (1.0, 0.8, 0.5 + math.sqrt(3) / 4):
+        lam = (tau - 0.5) ** 2
+        for _ in range(5):
+            f = _random_cell(q, rng)
+            F = rng.uniform(-1e-3, 1e-3, 3)
+            rho = f.sum()
+            u = (c.T @ f + F / 2) / rho
+            feq = oracle.equilibrium(q, rho, u)
+            S = w * (3 * ((c - u) @ F) + 9 * (c @ u) * (c @ F))
+            expect = f - (f - feq) / tau + (1 - 1 / (2 * tau)) * S
+            fs, _ = oracle.collide(q, f, tau, lam, F)
+            assert np.allclose(fs, expect, rtol=0, atol=2e-16)
+
+
+def test_antisymmetric_rate_follows_magic():
+    """The odd (antisymmetric) part relaxes with w- = 1/(1/2 + magic/(tau - 1/2)):
+    for a cell with f = f_eq + g, g odd under c -> -c and moment-free, the
+    post-collision odd part is (1 - w-) g."""
+    q = 19
+    c, w, opp = oracle.velocity_set(q)
+    feq = oracle.equilibrium(q, 1.0, np.zeros(3))
+    # odd, zero first moment: the third-order Hermite-like mode c_x (c_y^2 - c_z^2)
+    g = 1e-4 * w * c[:, 0] * (c[:, 1] ** 2 - c[:, 2] ** 2)
+    assert abs((c.T @ g)).max() < 1e-18 and abs(g.sum()) < 1e-18
+    for tau, lam in ((0.6, MAGIC), (0.9, 0.25), (1.3, 0.05)):
+        wm = 1 / (0.5 + lam / (tau - 0.5))
+        fs, _ = oracle.collide(q, feq + g, tau, lam)
+        assert np.allclose(fs - feq, (1 - wm) * g, rtol=0, atol=3e-16)
+
+
+# --------------------------------------------------------------------------
+# closed-form flows
+# --------------------------------------------------------------------------
+def _poiseuille(q, tau, magic, ny=16, nx=1, nz=1, F=1e-5):
+    nu = (tau - 0.5) / 3
+    y = np.arange(ny)
+    exact = F / (2 * nu) * (y + 0.5) * (ny - 0.5 - y)
+    sim = oracle.Sim(q, (nx, ny, nz), bc=(0, 0, BC_NOSLIP, BC_NOSLIP, 0, 0), tau=tau, magic=magic,
+                     force=(F, 0, 0))
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = exact[None, :, None]
+    sim.init_equilibrium(np.ones((nz, ny, nx)), u)
+    steps = int(6 * ny * ny / nu)
+    sim.step(steps)
+    _, uu = sim.moments()
+    return uu[0, 0, :, 0], exact, uu
+
+
+@pytest.mark.parametrize("q", QS)
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.0, 1.5])
+def test_poiseuille_exact_with_magic_3_16(q, tau):
+    # exact up to the roundoff accumulated over ~5e4 FP64 steps (measured <= 4e-12)
+    got, exact, uu = _poiseuille(q, tau, MAGIC)
+    assert np.max(np.abs(got - exact)) / exact.max() < 2e-11
+    assert np.abs(uu[1:]).max() < 1e-13
+
+
+def test_poiseuille_bgk_equivalent_point():
+    """BGK at tau = 1/2 + sqrt(3)/4 has (tau - 1/2)^2 = 3/16 and must give the
+    same exact parabola."""
+    tau = 0.5 + math.sqrt(3) / 4
+    got, exact, _ = _poiseuille(19, tau, (tau - 0.5) ** 2)
+    assert np.max(np.abs(got - exact)) / exact.max() < 2e-11
+
+
+def test_poiseuille_negative_control_other_magic():
+    """Any other magic parameter moves the bounce-back wall: a visible slip."""
+    got, exact, _ = _poiseuille(19, 1.0, 0.25)
+    assert np.max(np.abs(got - exact)) / exact.max() > 1e-3
+
+
+def _tgv_rate(n, nu, u0, t0, t1, q=19):
+    tau = 3 * nu + 0.5
+    sim = oracle.Sim(q, (n, n, 1), tau=tau, magic=MAGIC)
+    rho, u = inputs.taylor_green(n, n, 1, u0)
+    sim.init_equilibrium(rho, u)
+    k = 2 * math.pi / n
+    x = np.arange(n)[None, :]
+    y = np.arange(n)[:, None]
+    mode = np.cos(k * x) * np.sin(k * y)
+
+    def amp():
+        _, uu = sim.moments()
+        return (uu[0, 0] * mode).sum() / (mode * mode).sum()
+
+    sim.step(t0)
+    a0 = amp()
+    sim.step(t1 - t0)
+    a1 = amp()
+    rate = -math.log(a1 / a0) / (t1 - t0)
+    return rate / (2 * k * k)
+
+
+@pytest.mark.parametrize("q", QS)
+def test_taylor_green_decay_rate(q):
+    """Velocity amplitude decays as exp(-2 nu k^2 t): nu = 0.01, u0 = 0.05, 32^2."""
+    nu = 0.01
+    e32 = _tgv_rate(32, nu, 0.05, 100, 1000, q) / nu - 1
+    assert abs(e32) < 0.01
+
+
+def test_taylor_green_second_order():
+    """In the linear regime (u0 = 1e-4, no Mach-number error) the decay-rate
+    error falls by 4 when the grid is refined by 2 at fixed lattice viscosity
+    (diffusive scaling, times x4)."""
+    nu = 0.01
+    e32 = _tgv_rate(32, nu, 1e-4, 100, 1000) / nu - 1
+    e64 = _tgv_rate(64, nu, 1e-4, 400, 4000) / nu - 1
+    assert 3.6 < e32 / e64 < 4.4, (e32, e64)
+
+
+# --------------------------------------------------------------------------
+# conservation, symmetry, boundary conditions
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("q", QS)
+def test_mass_conserved_walls_and_solids(q):
+    nx, ny, nz = 8, 10, 6
+    rng = np.random.default_rng(5)
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[2:4, 3:6, 2:5] = 1
+    sim = oracle.Sim(q, (nx, ny, nz), bc=(0, 0, BC_NOSLIP, BC_NOSLIP, 0, 0), tau=0.7, force=(1e-5, 2e-6, 0),
+                     solid=solid)
+    rho = 1 + rng.uniform(-0.02, 0.02, (nz, ny, nx))
+    u = rng.uniform(-0.05, 0.05, (3, nz, ny, nx))
+    sim.init_equilibrium(rho, u)
+    m0, _ = sim.totals()
+    sim.step(200)
+    m1, _ = sim.totals()
+    assert abs(m1 - m0) / m0 < 1e-13
+
+
+@pytest.mark.parametrize("q", QS)
+def test_momentum_grows_by_force_fully_periodic(q):
+    nx, ny, nz = 6, 5, 4
+    rng = np.random.default_rng(6)
+    F = np.array([1e-5, -3e-6, 2e-6])
+    sim = oracle.Sim(q, (nx, ny, nz), tau=0.8, force=F)
+    rho = 1 + rng.uniform(-0.02, 0.02, (nz, ny, nx))
+    u = rng.uniform(-0.05, 0.05, (3, nz, ny, nx))
+    sim.init_equilibrium(rho, u)
+    _, p0 = sim.totals()
+    steps = 50
+    sim.step(steps)
+    _, p1 = sim.totals()
+    N = nx * ny * nz
+    # roundoff of sums over N * q values of size ~0.03 (measured <= 7e-14)
+    assert np.allclose(p1 - p0, steps * N * F, rtol=0, atol=1e-12)
+
+
+def test_tgv_total_momentum_stays_zero():
+    sim = oracle.Sim(19, (16, 16, 4), tau=0.53)
+    sim.init_equilibrium(*inputs.taylor_green(16, 16, 4))
+    sim.step(100)
+    _, p = sim.totals()
+    assert np.abs(p).max() < 1e-13
+
+
+def test_channel_mirror_symmetry():
+    """A noise-free channel stays mirror-symmetric about its mid-plane."""
+    nx, ny, nz = 8, 12, 4
+    rho, u = inputs.channel(nx, ny, nz, u_c=0.05, noise=0.0)
+    # an asymmetric-in-x but y-symmetric perturbation of v keeps the mirror property v(y) = -v(ny-1-y)
+    yy = np.arange(ny) - (ny - 1) / 2
+    u[1] += 1e-3 * np.sin(2 * np.pi * np.arange(nx) / nx)[None, None, :] * np.sign(yy)[None, :, None]
+    sim = oracle.Sim(19, (nx, ny, nz), bc=(0, 0, BC_NOSLIP, BC_NOSLIP, 0, 0), tau=0.6, force=(1e-6, 0, 0))
+    sim.init_equilibrium(rho, u)
+    sim.step(300)
+    r, uu = sim.moments()
+    assert np.allclose(uu[0], uu[0][:, ::-1, :], rtol=0, atol=1e-15)
+    assert np.allclose(uu[1], -uu[1][:, ::-1, :], rtol=0, atol=1e-15)
+    assert np.allclose(r, r[:, ::-1, :], rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("q", QS)
+def test_inflow_outflow_plug_flow(q):
+    """Velocity inlet at -x and pressure outlet at +x with periodic y, z: the
+    uniform state rho = 1, u = u_w is a fixed point and perturbations decay
+    back to it."""
+    nx, ny, nz = 24, 4, 3
+    uw = np.zeros((6, 3))
+    uw[0] = (0.04, 0, 0)
+    sim = oracle.Sim(q, (nx, ny, nz), bc=(BC_VELOCITY, BC_PRESSURE, 0, 0, 0, 0), tau=0.8, u_bc=uw)
+    rho, u = inputs.uniform_flow(nx, ny, nz, (0.04, 0, 0))
+    sim.init_equilibrium(rho, u)
+    sim.step(5)
+    r, uu = sim.moments()
+    assert np.abs(uu[0] - 0.04).max() < 1e-15 and np.abs(r - 1).max() < 1e-15
+    # perturbed start relaxes back to the plug
+    u2 = u + inputs.perturbation(u.shape, 0.004, seed=9)
+    rho2 = rho + inputs.perturbation(rho.shape, 0.002, seed=10)
+    sim.init_equilibrium(rho2, u2)
+    sim.step(6000)
+    r, uu = sim.moments()
+    assert np.abs(uu[0] - 0.04).max() < 1e-6
+    assert np.abs(uu[1:]).max() < 1e-6
+    assert np.abs(r - 1).max() < 1e-6
+
+
+def test_solid_rows_equal_wall_faces():
+    """A channel walled by solid rows equals the same channel walled by no-slip faces."""
+    nx, ny, nz = 6, 10, 4
+    rho, u = inputs.channel(nx, ny, nz, u_c=0.03, noise=0.05, seed=4)
+    a = oracle.Sim(19, (nx, ny, nz), bc=(0, 0, BC_NOSLIP, BC_NOSLIP, 0, 0), tau=0.7, force=(2e-6, 0, 0))
+    a.init_equilibrium(rho, u)
+    solid = np.zeros((nz, ny + 2, nx), np.uint8)
+    solid[:, 0] = 1
+    solid[:, -1] = 1
+    rho_b = np.ones((nz, ny + 2, nx))
+    rho_b[:, 1:-1] = rho
+    u_b = np.zeros((3, nz, ny + 2, nx))
+    u_b[:, :, 1:-1] = u
+    b = oracle.Sim(19, (nx, ny + 2, nz), tau=0.7, force=(2e-6, 0, 0), solid=solid)
+    b.init_equilibrium(rho_b, u_b)
+    a.step(100)
+    b.step(100)
+    fa = a.get_pdfs()
+    fb = b.get_pdfs()[:, :, 1:-1, :]
+    assert np.array_equal(fa, fb)
+
+
+@pytest.mark.parametrize("q", QS)
+def test_probe_matches_full_steps(q):
+    """The k-step probe (pull form) equals k full steps (push form) on a small
+    domain with every boundary kind, solids and a closure."""
+    nx, ny, nz = 7, 6, 5
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[2, 2:4, 3] = 1
+    uw = np.zeros((6, 3))
+    uw[0] = (0.03, 0.005, 0)
+    rng = np.random.default_rng(8)
+    rho = 1 + rng.uniform(-0.01, 0.01, (nz, ny, nx))
+    u = rng.uniform(-0.04, 0.04, (3, nz, ny, nx))
+    for bc, closure in (((BC_VELOCITY, BC_PRESSURE, BC_NOSLIP, BC_NOSLIP, 0, 0), oracle.CL_NONE),
+                        ((0, 0, BC_NOSLIP, BC_VELOCITY, BC_PRESSURE, BC_PRESSURE), oracle.CL_SMAG)):
+        kw = dict(bc=bc, tau=0.62, force=(1e-4, -2e-5, 3e-5), u_bc=uw, solid=solid, closure=closure, cs=0.15)
+        full = oracle.Sim(q, (nx, ny, nz), **kw)
+        full.init_equilibrium(rho, u)
+        cells = np.flatnonzero(solid.reshape(-1) == 0)
+        for k in (1, 2):
+            full.step(1)
+            got = oracle.Sim(q, (nx, ny, nz), **kw).probe(rho, u, k, cells)
+            ref = full.get_pdfs().reshape(q, -1)[:, cells].T
+            assert np.all(np.isfinite(got))
+            assert np.allclose(got, ref, rtol=0, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Smagorinsky closure
+# --------------------------------------------------------------------------
+def test_smagorinsky_quadratic_and_limits():
+    rng = np.random.default_rng(11)
+    for _ in range(50):
+        tau, cs, Q, rho = rng.uniform(0.5, 1.5), rng.uniform(0, 0.3), rng.uniform(0, 1e-2), rng.uniform(0.9, 1.1)
+        tt = oracle.smagorinsky_tau(tau, cs, Q, rho)
+        assert abs(tt * tt - tau * tt - 4.5 * math.sqrt(2) * cs * cs * Q / rho) < 1e-15
+        assert tt >= tau
+    assert oracle.smagorinsky_tau(0.7, 0.0, 1e-3, 1.0) == 0.7
+
+
+def test_noneq_flux_from_hermite_state():
+    """For f = f_eq + (w_i / (2 c_s^4)) (c c - c_s^2 I) : Pi the non-equilibrium
+    flux recovered by the collision is exactly Pi (F = 0), and the closure
+    uses tau_tot of Q = |Pi|."""
+    for q in QS:
+        c, w, _ = oracle.velocity_set(q)
+        rng = np.random.default_rng(12)
+        A = rng.uniform(-1e-3, 1e-3, (3, 3))
+        Pi = A + A.T
+        rho, u = 1.02, np.array([0.03, -0.01, 0.02])
+        feq = oracle.equilibrium(q, rho, u)
+        H = np.einsum("ia,ib->iab", c, c) - np.eye(3)[None] / 3
+        fne = w / (2 / 9) * np.einsum("iab,ab->i", H, Pi)
+        P6 = oracle.noneq_flux(q, feq + fne)
+        assert np.allclose(P6, [Pi[0, 0], Pi[1, 1], Pi[2, 2], Pi[0, 1], Pi[0, 2], Pi[1, 2]], atol=1e-16)
+        tau, cs = 0.6, 0.1
+        _, tt = oracle.collide(q, feq + fne, tau, MAGIC, closure=oracle.CL_SMAG, cs=cs)
+        Q = np.sqrt((Pi * Pi).sum())
+        assert abs(tt - 0.5 * (tau + math.sqrt(tau * tau + 18 * math.sqrt(2) * cs * cs * Q / rho))) < 1e-15
+        # Cs = 0 is the plain collision, bit for bit
+        a, _ = oracle.collide(q, feq + fne, tau, MAGIC, closure=oracle.CL_SMAG, cs=0.0)
+        b, _ = oracle.collide(q, feq + fne, tau, MAGIC)
+        assert np.array_equal(a, b)
+
+
+def test_features_invariant_under_rotation():
+    rng = np.random.default_rng(13)
+    A = rng.uniform(-1e-3, 1e-3, (3, 3))
+    P = A + A.T
+    Rq, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    P2 = Rq @ P @ Rq.T
+
+    def pack(M):
+        return np.array([M[0, 0], M[1, 1], M[2, 2], M[0, 1], M[0, 2], M[1, 2]])
+
+    x1 = oracle.features(pack(P), 1.01, 0.55, 0.1)
+    x2 = oracle.features(pack(P2), 1.01, 0.55, 0.1)
+    assert np.allclose(x1, x2, rtol=1e-10, atol=1e-18)
+    # diagonal closed form
+    d = np.array([3e-4, -1e-4, 1e-4])
+    x = oracle.features(np.r_[d, 0, 0, 0], 1.0, 0.6, 0.1)
+    dev = d - d.mean()
+    assert abs(x[0] - d.sum()) < 1e-18
+    assert abs(x[1] - np.linalg.norm(dev)) < 1e-18
+    assert abs(x[2] - np.cbrt(np.prod(dev))) < 1e-15
+    assert x[3] == 0.0 and x[5] == 0.6
+
+
+# --------------------------------------------------------------------------
+# MLP
+# --------------------------------------------------------------------------
+def _mlp_params(seed=0):
+    rng = np.random.default_rng(seed)
+    p = np.concatenate([rng.normal(0, 0.4, 192), rng.normal(0, 0.1, 32), rng.normal(0, 0.2, 1024),
+                        rng.normal(0, 0.1, 32), rng.normal(0, 0.3, 32), [-2.0]])
+    norm = np.concatenate([rng.normal(0, 1, 6), rng.uniform(0.5, 2, 6), -1e9 * np.ones(6), 1e9 * np.ones(6)])
+    return p, norm
+
+
+def test_mlp_gradient_finite_differences():
+    p, norm = _mlp_params(1)
+    rng = np.random.default_rng(2)
+    x = rng.normal(0, 1, (16, 6))
+    t = rng.uniform(0, 0.2, 16)
+    loss, g = oracle.mlp_loss_grad(p, norm, x, t)
+    idx = np.r_[rng.choice(192, 8, False), 192 + rng.choice(32, 4, False), 224 + rng.choice(1024, 8, False),
+                1248 + rng.choice(32, 4, False), 1280 + rng.choice(32, 4, False), 1312]
+    for k in idx:
+        h = 1e-6
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (oracle.mlp_loss_grad(pp, norm, x, t)[0] - oracle.mlp_loss_grad(pm, norm, x, t)[0]) / (2 * h)
+        assert abs(fd - g[k]) <= 1e-6 * max(1e-3, abs(g[k])) + 1e-11, (k, fd, g[k])
+    # loss matches the forward
+    y = oracle.mlp_forward(p, norm, x)
+    assert abs(loss - np.mean((y - t) ** 2)) < 1e-15
+
+
+def test_mlp_single_path_closed_form():
+    """With one non-zero path the network is softplus(w3 tanh(w2 tanh(w1 z + b1) + b2) + b3)."""
+    p = np.zeros(1313)
+    norm = np.r_[np.zeros(6), np.ones(6), -np.ones(6) * 1e9, np.ones(6) * 1e9]
+    w1, b1, w2, b2, w3, b3 = 0.7, 0.1, -1.3, 0.2, 0.9, -0.4
+    p[0 * 6 + 2] = w1  # W1[0][2]
+    p[192 + 0] = b1
+    p[224 + 5 * 32 + 0] = w2  # W2[5][0]
+    p[1248 + 5] = b2
+    p[1280 + 5] = w3
+    p[1312] = b3
+    x = np.zeros((1, 6))
+    x[0, 2] = 0.35
+    h1 = math.tanh(w1 * 0.35 + b1)
+    h2_5 = math.tanh(w2 * h1 + b2)
+    others = 0.0
+    # every other hidden unit of layer 2 sees tanh(b2_j) = 0 (b2_j = 0): no contribution
+    o = w3 * h2_5 + b3 + others
+    assert abs(oracle.mlp_forward(p, norm, x)[0] - math.log1p(math.exp(o))) < 1e-15
+
+
+def _one_cell_step(q, f, **kw):
+    """A 1x1x1 fully periodic lattice streams every population onto itself,
+    so one step returns the post-collision state of that cell."""
+    sim = oracle.Sim(q, (1, 1, 1), **{k: v for k, v in kw.items() if k not in ("params", "norm")})
+    if "params" in kw:
+        sim.set_mlp(kw["params"], kw["norm"])
+    sim.set_pdfs(f.reshape(q, 1, 1, 1))
+    sim.step(1)
+    return sim.get_pdfs().reshape(q), sim
+
+
+def test_mlp_closure_in_collision():
+    """A network with constant output c = softplus(b3) gives exactly the plain
+    collision at tau + c; an input outside the stored range falls back to the
+    Smagorinsky collision."""
+    q = 19
+    rng = np.random.default_rng(21)
+    f = _random_cell(q, rng)
+    F = (1e-4, 0, -2e-5)
+    p = np.zeros(1313)
+    p[1312] = 0.3
+    c = math.log1p(math.exp(0.3))
+    norm = np.r_[np.zeros(6), np.ones(6), -np.ones(6) * 1e9, np.ones(6) * 1e9]
+    a, sa = _one_cell_step(q, f, tau=0.6, force=F, closure=oracle.CL_MLP, params=p, norm=norm)
+    b, _ = _one_cell_step(q, f, tau=0.6 + c, force=F)
+    assert np.allclose(a, b, rtol=0, atol=1e-16) and sa.fallbacks == 0
+    norm2 = norm.copy()
+    norm2[18 + 5] = 0.5  # tau = 0.6 lies above the stored maximum of input 6
+    a, sa = _one_cell_step(q, f, tau=0.6, force=F, closure=oracle.CL_MLP, params=p, norm=norm2)
+    b, _ = _one_cell_step(q, f, tau=0.6, force=F, closure=oracle.CL_SMAG)
+    assert np.array_equal(a, b) and sa.fallbacks == 1
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(3)
+    v = np.r_[rng.normal(0, 1, 2000), rng.normal(0, 1e-3, 500), [1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 0.0, -2.5]]
+    v32 = v.astype(np.float32).astype(np.float64)
+    ours = np.array([oracle.round_bf16(a) for a in v32])
+    ref = torch.tensor(v32, dtype=torch.float32).bfloat16().double().numpy()
+    assert np.array_equal(ours, ref)
+
+
+def test_adam_first_step_closed_form():
+    """After the first update, m_hat = g and v_hat = g^2, so every component
+    moves by lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(4)
+    p = rng.normal(size=50)
+    g = rng.normal(size=50)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    p0 = p.copy()
+    oracle.adam(p, g, m, v, 1, 1e-3)
+    assert np.allclose(p0 - p, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# training-data builders
+# --------------------------------------------------------------------------
+def test_box_filter_invariants():
+    rng = np.random.default_rng(5)
+    nz, ny, nx = 8, 12, 16
+    rho = np.full((nz, ny, nx), 1.25)
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = 0.3
+    out = oracle.box_filter4(rho, u)
+    assert np.allclose(out[0], 1.25) and np.allclose(out[1], 0.3) and np.allclose(out[4], 0.09)
+    rho = rng.uniform(0.9, 1.1, (nz, ny, nx))
+    u = rng.uniform(-0.1, 0.1, (3, nz, ny, nx))
+    out = oracle.box_filter4(rho, u)
+    assert abs(out[0].sum() * 64 - rho.sum()) < 1e-11
+    # linear field -> value at the block centre
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    u = np.stack([0.01 * x, 0.02 * y - 0.1, -0.03 * z])
+    out = oracle.box_filter4(np.ones((nz, ny, nx)), u)
+    cz, cy, cx = np.meshgrid(np.arange(nz // 4), np.arange(ny // 4), np.arange(nx // 4), indexing="ij")
+    assert np.allclose(out[1], 0.01 * (4 * cx + 1.5), atol=1e-15)
+    assert np.allclose(out[2], 0.02 * (4 * cy + 1.5) - 0.1, atol=1e-15)
+    assert np.allclose(out[3], -0.03 * (4 * cz + 1.5), atol=1e-15)
+
+
+def test_strain_exact_on_quadratics():
+    """Central differences are exact on quadratics; at a wall the one-sided rule
+    is exact on quadratics vanishing half a cell outside."""
+    cz, cy, cx = 4, 8, 6
+    z, y, x = np.meshgrid(np.arange(cz), np.arange(cy), np.arange(cx), indexing="ij")
+    H = cy
+    u = np.zeros((3, cz, cy, cx))
+    u[0] = (y + 0.5) * (H - 0.5 - y)      # zero on both y walls
+    u[2] = 0.3 * (y + 0.5) ** 2          # zero on the low wall only: exact there
+    S = oracle.strain(u, periodic=(1, 0, 1))
+    dudy = H - 1 - 2 * y
+    assert np.allclose(S[3], 0.5 * dudy, atol=1e-13)
+    assert np.allclose(S[5][:, 0], 0.5 * 0.6 * 0.5, atol=1e-13)
+    assert np.allclose(S[5][:, 1:-1], 0.5 * 0.6 * (y[:, 1:-1] + 0.5), atol=1e-13)
+    assert np.allclose(S[0], 0) and np.allclose(S[1], 0) and np.allclose(S[2], 0)
+
+
+def test_closure_dataset_pure_shear():
+    """Filtered fields with <u'v'> = -c S_xy give nu_t* = c / 2 and dtau* = 3c/2."""
+    cz, cy, cx = 2, 6, 4
+    z, y, x = np.meshgrid(np.arange(cz), np.arange(cy), np.arange(cx), indexing="ij")
+    g = 2e-3
+    filt = np.zeros((10, cz, cy, cx))
+    filt[0] = 1.0
+    filt[1] = g * (y - 2.5)  # linear shear on a periodic-free interior
+    cc = 0.01
+    Sxy = 0.5 * g
+    filt[4 + 3] = filt[1] * filt[2] - 2 * cc * Sxy  # <u v> = u v - 2 c S_xy -> tau_sgs_xy = -2 c S_xy
+    x6, t = oracle.closure_dataset(filt, periodic=(1, 1, 1), tau=0.55)
+    inner = (y.reshape(-1) > 0) & (y.reshape(-1) < cy - 1)
+    assert np.allclose(t[inner], 3 * cc, rtol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# input generators
+# --------------------------------------------------------------------------
+def test_spheres_generator():
+    m1, s1 = inputs.spheres(96, 64, 64, fill=0.1, x_margin=8, seed=7)
+    m2, s2 = inputs.spheres(96, 64, 64, fill=0.1, x_margin=8, seed=7)
+    assert np.array_equal(m1, m2) and s1 == s2
+    assert m1.mean() >= 0.1
+    for i, (a, b, c, r) in enumerate(s1):
+        assert 6 <= r <= 20
+        for (a2, b2, c2, r2) in s1[i + 1:]:
+            assert (a - a2) ** 2 + (b - b2) ** 2 + (c - c2) ** 2 >= (r + r2 + 1) ** 2
+    assert not m1[:, :, :8].any() and not m1[:, :, -8:].any()
+
+
+def test_channel_generator_recipe():
+    rho, u = inputs.channel(8, 16, 4, u_c=0.05, noise=0.0)
+    prof = u[0, 0, :, 0]
+    assert abs(prof.max() - 0.05 * (1 - 1 / 256)) < 1e-15  # centre of an even channel is between rows
+    assert np.allclose(prof, prof[::-1])
+    _, un = inputs.channel(8, 16, 4, u_c=0.05, noise=0.05, seed=1)
+    d = un - u
+    assert np.abs(d).max() <= 0.05 * 0.05 and np.abs(d).max() > 0.04 * 0.05
