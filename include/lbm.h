@@ -1,0 +1,228 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) lattice Boltzmann stream-collide library.
+ *
+ * The library advances the lattice Boltzmann equation of the paper
+ * ("Scalable Flow Simulations with the Lattice Boltzmann Method", Section 2,
+ * Eq. (1) collision and Eq. (2) streaming) on one GPU:
+ *   - D3Q19 or D3Q27 velocity set,
+ *   - two-relaxation-time collision (the paper's "Double Relaxation Time"
+ *     D3Q19 scheme of the LaBS section) with Guo body forcing,
+ *   - halfway bounce-back walls, velocity and pressure faces, periodic faces,
+ *     and an optional per-cell solid mask,
+ *   - one population set kept in place in HBM (AA access pattern, the family
+ *     of in-place schemes the paper's Esoteric Twist belongs to, Section 5.2),
+ *     structure-of-arrays layout [q][z][y][x],
+ *   - optional LES closures (Smagorinsky, or a small learned MLP) that set a
+ *     per-cell relaxation time.
+ *
+ * Conventions for every entry point:
+ *   - Every pointer named *_dev is device memory on the current HIP device,
+ *     owned by the caller.  Pointers without the suffix are host memory.
+ *   - All work is enqueued on the stream given in lbm_domain (or the stream
+ *     argument of the free functions); entry points return once the work is
+ *     enqueued, except where a comment says "synchronises".
+ *   - The library never allocates device memory: a context lives in a
+ *     caller-provided workspace of lbm_workspace_bytes() bytes, which must
+ *     outlive the context.  lbm_destroy frees host metadata only.
+ *   - Calls on one context are not thread-safe.
+ *   - Every function returns LBM_OK (0) or a negative error code; the
+ *     message of the last error is available from lbm_last_error().
+ *   - Layouts: populations are canonical FP64 [q][nz][ny][nx] (x fastest),
+ *     the value f_i(x, t) after streaming and before collision.  Scalar
+ *     fields are [nz][ny][nx]; vector fields [3][nz][ny][nx].
+ *   - Velocity order (pairs (odd, odd+1) are opposite):
+ *       0 (0,0,0); 1,2 (+-1,0,0); 3,4 (0,+-1,0); 5,6 (0,0,+-1);
+ *       7 (1,1,0) 8 (-1,-1,0); 9 (1,-1,0) 10 (-1,1,0); 11 (1,0,1) 12 (-1,0,-1);
+ *       13 (1,0,-1) 14 (-1,0,1); 15 (0,1,1) 16 (0,-1,-1); 17 (0,1,-1) 18 (0,-1,1);
+ *       D3Q27 adds 19 (1,1,1) 20 (-1,-1,-1); 21 (1,1,-1) 22 (-1,-1,1);
+ *       23 (1,-1,1) 24 (-1,1,-1); 25 (-1,1,1) 26 (1,-1,-1).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)     /* invalid argument (sizes, enums, NULL, small workspace) */
+#define LBM_ENOMEM (-2)     /* the domain does not fit the 32-bit cell indexing or host memory */
+#define LBM_EDEVICE (-3)    /* a HIP runtime call or kernel launch failed */
+#define LBM_ENONFINITE (-4) /* lbm_totals found a NaN or Inf population */
+#define LBM_ESTATE (-5)     /* call not valid in the current state (e.g. MLP weights missing) */
+
+/* Velocity sets. */
+enum { LBM_D3Q19 = 19, LBM_D3Q27 = 27 };
+
+/* Per-face boundary kinds.  Faces are ordered -x, +x, -y, +y, -z, +z.
+ * Walls lie halfway between the first/last cell row and the face. */
+enum {
+    LBM_BC_PERIODIC = 0, /* wrap around; the opposite face must be periodic too */
+    LBM_BC_NOSLIP = 1,   /* halfway bounce-back */
+    LBM_BC_VELOCITY = 2, /* moving-wall bounce-back with u_bc and rho_bc of the face */
+    LBM_BC_PRESSURE = 3  /* anti-bounce-back with density rho_bc of the face */
+};
+
+/* Population storage in HBM.  All forms store the deviation f_i - w_i. */
+enum {
+    LBM_STORE_F32 = 0,     /* 4 bytes per population */
+    LBM_STORE_F16DEV = 1,  /* IEEE half, round to nearest even, subnormals kept */
+    LBM_STORE_BF16DEV = 2  /* bfloat16, round to nearest even */
+};
+
+/* Relaxation-time closures. */
+enum { LBM_LES_NONE = 0, LBM_LES_SMAGORINSKY = 1, LBM_LES_MLP = 2 };
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef struct lbm_domain {
+    int32_t nx, ny, nz;      /* cells, x fastest; each >= 1 */
+    int32_t bc[6];           /* LBM_BC_* per face -x,+x,-y,+y,-z,+z */
+    double u_bc[6][3];       /* wall velocity of velocity faces */
+    double rho_bc[6];        /* wall density of velocity and pressure faces (1.0 by default) */
+    int32_t storage;         /* LBM_STORE_* */
+    int32_t closure;         /* LBM_LES_* */
+    int32_t use_flags;       /* non-zero: reserve room for a per-cell solid mask */
+    double magic;            /* TRT magic parameter Lambda (3/16 by default) */
+    double cs_smag;          /* Smagorinsky constant (0.1 by default) */
+    void *workspace;         /* device memory of workspace_bytes bytes, 256-byte aligned */
+    size_t workspace_bytes;
+    void *stream;            /* hipStream_t; NULL = the default stream */
+} lbm_domain;
+
+/* Fill *d with defaults: all faces periodic, rho_bc = 1, u_bc = 0, F32
+ * storage, no closure, no flags, magic = 3/16, cs_smag = 0.1, no workspace. */
+void lbm_domain_defaults(lbm_domain *d);
+
+/* Bytes of device workspace a context needs for domain d and the stencil
+ * (19 or 27).  Only nx, ny, nz, storage, closure and use_flags are read. */
+int lbm_workspace_bytes(const lbm_domain *d, int stencil, size_t *out);
+
+/*
+ * Create a context.  tau > 1/2 is the molecular relaxation time
+ * (viscosity nu = (tau - 1/2)/3); force[3] (nullable: zero) is the constant
+ * body-force density of Guo's forcing; flags (host, nullable) holds one byte
+ * per cell, non-zero = solid, and needs d->use_flags.  Opposite faces must
+ * both be periodic or both not.  The populations are left undefined: call
+ * lbm_init_equilibrium or lbm_set_pdfs next.  Synchronises.
+ */
+int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double tau, const double force[3],
+               lbm_ctx **out);
+
+/* Release host metadata.  Device memory (the workspace) stays the caller's. */
+int lbm_destroy(lbm_ctx *ctx);
+
+/* Message of the last failure on ctx (ctx == NULL: of the last failed
+ * lbm_create on this thread).  Never NULL. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Set every fluid cell to the second-order equilibrium f_i^eq(rho, u) of
+ * the given FP64 fields (rho_dev [n], u_dev [3][n]); resets the step count
+ * to 0.  Equilibrium as in Eq. (1)'s f^eq with c_s^2 = 1/3. */
+int lbm_init_equilibrium(lbm_ctx *ctx, const double *rho_dev, const double *u_dev);
+
+/* Load canonical FP64 populations f_dev [q][n] (rounded to the storage
+ * format); resets the step count to 0. */
+int lbm_set_pdfs(lbm_ctx *ctx, const double *f_dev);
+
+/* Write the canonical FP64 populations of the current step to f_dev [q][n]
+ * (solid cells: w_i).  Valid after any number of steps. */
+int lbm_get_pdfs(lbm_ctx *ctx, double *f_dev);
+
+/* Canonical FP64 populations at n cells (linear indices cells_dev[n],
+ * int64) into out_dev [n][q]. */
+int lbm_gather_pdfs(lbm_ctx *ctx, const int64_t *cells_dev, int64_t n, double *out_dev);
+
+/* Advance n >= 0 time steps (Eq. (1) then Eq. (2) per step, fused in one
+ * kernel per step).  Asynchronous. */
+int lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Steps taken since the last init/set/load. */
+int64_t lbm_time(const lbm_ctx *ctx);
+
+/* Density rho_dev [n] and velocity u_dev [3][n] = (j + F/2)/rho of the
+ * current canonical state, FP32 (solid cells: rho = 1, u = 0). */
+int lbm_moments(lbm_ctx *ctx, float *rho_dev, float *u_dev);
+
+/* FP64 totals over fluid cells of the current state: *mass = sum rho,
+ * mom = sum_i c_i f_i.  Deterministic.  Synchronises.  Returns
+ * LBM_ENONFINITE if any fluid population is NaN or Inf. */
+int lbm_totals(lbm_ctx *ctx, double *mass, double mom[3]);
+
+/* Bytes of the raw population state (for checkpoints). */
+int lbm_state_bytes(const lbm_ctx *ctx, size_t *out);
+
+/* Copy the raw state to dst_dev (lbm_state_bytes bytes) and report the
+ * step count; lbm_load_state restores both.  A restored run continues bit
+ * for bit as the saved one would have. */
+int lbm_save_state(lbm_ctx *ctx, void *dst_dev, int64_t *time);
+int lbm_load_state(lbm_ctx *ctx, const void *src_dev, int64_t time);
+
+/*
+ * Learned-closure weights (host, FP32): n = 1313 + 24 values, the MLP
+ * 6 -> 32 -> 32 -> 1 as W1[32][6], b1[32], W2[32][32], b2[32], W3[32], b3,
+ * then per input mu[6], sigma[6], lo[6], hi[6] (standardisation and the
+ * trusted input range; outside it the cell falls back to Smagorinsky).
+ * Weights are rounded to bfloat16 for the matrix cores.  Synchronises.
+ */
+int lbm_set_closure_weights(lbm_ctx *ctx, const float *params, size_t n);
+
+/* Number of fluid-cell updates that fell back to Smagorinsky since the last
+ * call (MLP closure only); resets the counter.  Synchronises. */
+int lbm_closure_fallbacks(lbm_ctx *ctx, int64_t *count);
+
+/* ------------------------------------------------------------------------ */
+/* Training-data and training kernels of the learned closure.               */
+/* ------------------------------------------------------------------------ */
+
+/* Box filter over non-overlapping 4x4x4 blocks of fine FP32 fields
+ * rho_dev [n], u_dev [3][n] (nx, ny, nz multiples of 4) into out_dev
+ * [10][n/64] FP32: rho, u_x, u_y, u_z, then the filtered products uu in
+ * the order xx, yy, zz, xy, xz, yz. */
+int lbm_box_filter4(int32_t nx, int32_t ny, int32_t nz, const float *rho_dev, const float *u_dev, float *out_dev,
+                    void *stream);
+
+/* Closure dataset from filtered coarse fields filt_dev [10][n] (cx, cy, cz
+ * cells, periodic[3] per axis; non-periodic axes have walls halfway outside
+ * the first/last cell): features x_dev [n][6] and target dtau t_dev [n],
+ * FP32.  tau is the molecular relaxation time of the coarse lattice, cs the
+ * Smagorinsky constant used for feature 5. */
+int lbm_closure_dataset(int32_t cx, int32_t cy, int32_t cz, const int32_t periodic[3], const float *filt_dev,
+                        double tau, double cs, float *x_dev, float *t_dev, void *stream);
+
+/* MLP forward over a batch: params_dev (1313 + 24 FP32, layout as in
+ * lbm_set_closure_weights), x_dev [n][6] -> y_dev [n] FP32.  Matrix
+ * products on bfloat16 matrix cores with FP32 accumulation. */
+int lbm_mlp_forward(const float *params_dev, const float *x_dev, int64_t n, float *y_dev, void *stream);
+
+/* Mean-squared-error loss over the batch and its gradient with respect to
+ * the 1313 parameters: grad_dev [1313] FP32 (overwritten), loss_dev [1]
+ * FP32.  Deterministic (fixed reduction order).  work_dev must hold
+ * lbm_mlp_work_bytes(n) bytes. */
+size_t lbm_mlp_work_bytes(int64_t n);
+int lbm_mlp_loss_grad(const float *params_dev, const float *x_dev, const float *t_dev, int64_t n, float *grad_dev,
+                      float *loss_dev, void *work_dev, void *stream);
+
+/* One Adam step on the first 1313 entries of params_dev with FP32 moment
+ * buffers m_dev, v_dev [1313]; step is 1-based. */
+int lbm_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int64_t step, double lr,
+                 double beta1, double beta2, double eps, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Measurement helper.                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Plain device copy of bytes (multiple of 16) from src_dev to dst_dev: the
+ * device analogue of the STREAM copy the paper uses to measure the machine
+ * bandwidth b_s of its roofline P_max = b_s / n_b (Section 5.2, Eq. (3)). */
+int lbm_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -349,9 +349,15 @@ orc_sim *orc_create(int q, int nx, int ny, int nz, const int *bc, const double *
         s->solid = (unsigned char *)malloc((size_t)s->n);
         memcpy(s->solid, solid, (size_t)s->n);
     }
-    s->f = (double *)calloc((size_t)(q * s->n), sizeof(double));
-    s->g = (double *)calloc((size_t)(q * s->n), sizeof(double));
+    /* the two lattices are allocated on first use, so that a probe-only */
+    /* simulation of a large domain holds no population arrays           */
     return s;
+}
+
+static void ensure_lattices(orc_sim *s)
+{
+    if (!s->f) s->f = (double *)calloc((size_t)(s->q * s->n), sizeof(double));
+    if (!s->g) s->g = (double *)calloc((size_t)(s->q * s->n), sizeof(double));
 }
 
 void orc_destroy(orc_sim *s)
@@ -376,6 +382,7 @@ int64_t orc_fallbacks(const orc_sim *s) { return s->fallbacks; }
 void orc_init_equilibrium(orc_sim *s, const double *rho, const double *u)
 {
     double feq[27], uc[3];
+    ensure_lattices(s);
     for (int64_t c = 0; c < s->n; ++c) {
         for (int a = 0; a < 3; ++a) uc[a] = u[a * s->n + c];
         orc_equilibrium(s->q, rho[c], uc, feq);
@@ -383,8 +390,17 @@ void orc_init_equilibrium(orc_sim *s, const double *rho, const double *u)
     }
 }
 
-void orc_set_pdfs(orc_sim *s, const double *f) { memcpy(s->f, f, sizeof(double) * s->q * s->n); }
-void orc_get_pdfs(const orc_sim *s, double *f) { memcpy(f, s->f, sizeof(double) * s->q * s->n); }
+void orc_set_pdfs(orc_sim *s, const double *f)
+{
+    ensure_lattices(s);
+    memcpy(s->f, f, sizeof(double) * s->q * s->n);
+}
+
+void orc_get_pdfs(orc_sim *s, double *f)
+{
+    ensure_lattices(s);
+    memcpy(f, s->f, sizeof(double) * s->q * s->n);
+}
 
 /*
  * Collide one cell: f[q] in, fstar[q] out; u_out receives the cell velocity
@@ -557,6 +573,7 @@ static double push_target(const orc_sim *s, int x, int y, int z, int i, double v
  */
 void orc_step(orc_sim *s, int64_t nsteps)
 {
+    ensure_lattices(s);
     int q = s->q;
     int64_t N = s->n;
     for (int64_t t = 0; t < nsteps; ++t) {
@@ -585,8 +602,9 @@ void orc_step(orc_sim *s, int64_t nsteps)
 }
 
 /* Density and velocity u = (j + F/2)/rho of the canonical state; u [3][n]. */
-void orc_moments(const orc_sim *s, double *rho, double *u)
+void orc_moments(orc_sim *s, double *rho, double *u)
 {
+    ensure_lattices(s);
     int64_t N = s->n;
     for (int64_t c = 0; c < N; ++c) {
         double r = 0.0, j[3] = {0, 0, 0};
@@ -601,8 +619,9 @@ void orc_moments(const orc_sim *s, double *rho, double *u)
 }
 
 /* Totals over fluid cells: mass = sum rho, mom = sum j (raw first moment). */
-void orc_totals(const orc_sim *s, double *mass, double *mom)
+void orc_totals(orc_sim *s, double *mass, double *mom)
 {
+    ensure_lattices(s);
     int64_t N = s->n;
     double m = 0.0, p[3] = {0, 0, 0};
     for (int64_t c = 0; c < N; ++c) {

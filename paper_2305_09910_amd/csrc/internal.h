@@ -1,0 +1,73 @@
+// internal.h -- launch interface between the C ABI (lbm_api.cpp) and the
+// HIP kernels (lbm_kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+enum { CL_NONE = 0, CL_SMAG = 1, CL_MLP = 2 };
+enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
+
+// Bit 31 of a cell's mask word marks the cell itself as solid; bit i
+// (1 <= i < q) marks the neighbour x + c_i (reached through periodic faces
+// only) as solid.
+constexpr uint32_t SELF_SOLID = 0x80000000u;
+
+// MLP closure parameter block in device memory (FP32), see lbm.h.
+constexpr int MLP_NPARAM = 1313;
+constexpr int MLP_NNORM = 24;
+
+// Everything a lattice kernel needs, passed by value.
+struct LatticeArgs {
+    void *pdf;               // [q][n] storage elements (deviations f_i - w_i)
+    const uint32_t *mask;    // [n] or nullptr
+    int nx, ny, nz;
+    uint32_t n;              // cells
+    uint64_t plane;          // elements per direction plane (== n)
+    int per[3];              // axis periodic?
+    int bc[6];               // face kinds
+    int any_vp;              // any velocity / pressure face
+    float ubc[6][3];
+    float rhobc[6];
+    float F[3];
+    float tau, magic, cs;    // molecular tau, TRT magic, Smagorinsky constant
+    float omp, omm;          // omega+ and omega- of the molecular tau
+    const float *mlp;        // closure parameters (device) or nullptr
+    unsigned long long *fallbacks;  // MLP fallback counter (device) or nullptr
+};
+
+struct Launch {
+    dim3 grid, block;
+};
+Launch lattice_launch(const LatticeArgs &a);
+
+// Kernel launchers (return hipError_t of the launch).
+hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, uint32_t *mask, hipStream_t s);
+hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int odd, hipStream_t s);
+hipError_t launch_init_eq(const LatticeArgs &a, int q, int st, const double *rho, const double *u, hipStream_t s);
+hipError_t launch_set_pdfs(const LatticeArgs &a, int q, int st, const double *f, hipStream_t s);
+hipError_t launch_get_pdfs(const LatticeArgs &a, int q, int st, int odd, double *f, hipStream_t s);
+hipError_t launch_gather(const LatticeArgs &a, int q, int st, int odd, const int64_t *cells, int64_t ncell,
+                         double *out, hipStream_t s);
+hipError_t launch_moments(const LatticeArgs &a, int q, int st, int odd, float *rho, float *u, hipStream_t s);
+// totals: partial[nblk][5] doubles then final[5] = {sum drho, jx, jy, jz, nonfinite-count}
+int totals_blocks();
+hipError_t launch_totals(const LatticeArgs &a, int q, int st, int odd, double *partial, double *final_out,
+                         hipStream_t s);
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+// closure training path (lbm_closure.hip)
+hipError_t launch_box_filter4(int nx, int ny, int nz, const float *rho, const float *u, float *out, hipStream_t s);
+hipError_t launch_closure_dataset(int cx, int cy, int cz, const int *per, const float *filt, float tau, float cs,
+                                  float *x, float *t, hipStream_t s);
+hipError_t launch_mlp_forward(const float *params, const float *x, int64_t n, float *y, hipStream_t s);
+size_t mlp_work_bytes(int64_t n);
+hipError_t launch_mlp_loss_grad(const float *params, const float *x, const float *t, int64_t n, float *grad,
+                                float *loss, void *work, hipStream_t s);
+hipError_t launch_mlp_adam(float *p, const float *g, float *m, float *v, int64_t step, float lr, float b1, float b2,
+                           float eps, hipStream_t s);
+
+}  // namespace lbm

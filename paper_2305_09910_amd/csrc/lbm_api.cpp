@@ -1,0 +1,418 @@
+// lbm_api.cpp -- the C ABI declared in include/lbm.h.
+//
+// Host-side validation, workspace carve-up and kernel launches on the
+// caller's stream.  The library allocates no device memory: everything lives
+// in the caller's workspace.  Layout of the workspace (each part 256-byte
+// aligned):
+//   populations  q * n storage elements, [q][z][y][x]
+//   mask         n uint32 words (only with use_flags)
+//   totals       partial sums (1024 blocks x 5 doubles) and the final 5
+//   closure      MLP parameters (1313 + 24 FP32) and a fallback counter
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/lbm.h"
+#include "internal.h"
+
+using namespace lbm;
+
+struct lbm_ctx {
+    LatticeArgs a;
+    int q, st, cl;
+    int64_t time;
+    hipStream_t stream;
+    char *ws;
+    size_t ws_bytes;
+    double *partial, *final_out;
+    float *mlp;
+    unsigned long long *fallbacks;
+    uint32_t *mask;
+    int64_t nfluid;
+    int mlp_ready;
+    size_t state_bytes;
+    char err[512];
+};
+
+static thread_local char g_err[512] = "";
+
+static int fail(lbm_ctx *c, int code, const char *fmt, ...)
+{
+    char *buf = c ? c->err : g_err;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static int hip_fail(lbm_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHECK(c, call, what)                         \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(c, e_, what); \
+    } while (0)
+
+static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t pdf, mask, partial, final_out, mlp, fallback, total, pdf_bytes;
+};
+
+static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c)
+{
+    if (!d) return fail(c, LBM_EINVAL, "domain is NULL");
+    if (q != 19 && q != 27) return fail(c, LBM_EINVAL, "stencil must be 19 or 27, got %d", q);
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+        return fail(c, LBM_EINVAL, "domain sizes must be >= 1 (got %d x %d x %d)", d->nx, d->ny, d->nz);
+    if (d->storage < LBM_STORE_F32 || d->storage > LBM_STORE_BF16DEV)
+        return fail(c, LBM_EINVAL, "unknown storage %d", d->storage);
+    if (d->closure < LBM_LES_NONE || d->closure > LBM_LES_MLP)
+        return fail(c, LBM_EINVAL, "unknown closure %d", d->closure);
+    const uint64_t n = (uint64_t)d->nx * (uint64_t)d->ny * (uint64_t)d->nz;
+    if (n >= (1ull << 31)) return fail(c, LBM_ENOMEM, "domain of %llu cells exceeds 2^31 cells", (unsigned long long)n);
+    const size_t elem = d->storage == LBM_STORE_F32 ? 4 : 2;
+    size_t off = 0;
+    L->pdf = off;
+    L->pdf_bytes = (size_t)q * n * elem;
+    off += al256(L->pdf_bytes);
+    L->mask = off;
+    if (d->use_flags) off += al256(4 * n);
+    L->partial = off;
+    off += al256((size_t)totals_blocks() * 5 * sizeof(double));
+    L->final_out = off;
+    off += al256(5 * sizeof(double));
+    L->mlp = off;
+    off += al256((MLP_NPARAM + MLP_NNORM) * sizeof(float));
+    L->fallback = off;
+    off += 256;
+    L->total = off;
+    return LBM_OK;
+}
+
+extern "C" {
+
+void lbm_domain_defaults(lbm_domain *d)
+{
+    if (!d) return;
+    memset(d, 0, sizeof *d);
+    for (int f = 0; f < 6; ++f) {
+        d->bc[f] = LBM_BC_PERIODIC;
+        d->rho_bc[f] = 1.0;
+    }
+    d->storage = LBM_STORE_F32;
+    d->closure = LBM_LES_NONE;
+    d->magic = 3.0 / 16.0;
+    d->cs_smag = 0.1;
+}
+
+int lbm_workspace_bytes(const lbm_domain *d, int stencil, size_t *out)
+{
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    Layout L;
+    int rc = make_layout(d, stencil, &L, nullptr);
+    if (rc) return rc;
+    *out = L.total;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double tau, const double force[3],
+               lbm_ctx **out)
+{
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    int rc = make_layout(d, stencil, &L, nullptr);
+    if (rc) return rc;
+    if (!(tau > 0.5) || !isfinite(tau)) return fail(nullptr, LBM_EINVAL, "tau must be > 1/2 (got %g)", tau);
+    if (!(d->magic > 0.0) || !isfinite(d->magic)) return fail(nullptr, LBM_EINVAL, "magic must be > 0");
+    if (d->closure != LBM_LES_NONE && !(d->cs_smag >= 0.0)) return fail(nullptr, LBM_EINVAL, "cs_smag must be >= 0");
+    for (int f = 0; f < 6; ++f)
+        if (d->bc[f] < LBM_BC_PERIODIC || d->bc[f] > LBM_BC_PRESSURE)
+            return fail(nullptr, LBM_EINVAL, "unknown boundary kind %d on face %d", d->bc[f], f);
+    for (int a = 0; a < 3; ++a)
+        if ((d->bc[2 * a] == LBM_BC_PERIODIC) != (d->bc[2 * a + 1] == LBM_BC_PERIODIC))
+            return fail(nullptr, LBM_EINVAL, "axis %d: a periodic face needs a periodic opposite face", a);
+    if (flags && !d->use_flags) return fail(nullptr, LBM_EINVAL, "flags given but domain.use_flags is 0");
+    if (!d->workspace) return fail(nullptr, LBM_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d->workspace & 255) != 0) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
+    if (d->workspace_bytes < L.total)
+        return fail(nullptr, LBM_EINVAL, "workspace too small: %zu < %zu bytes", d->workspace_bytes, L.total);
+    if (force)
+        for (int a = 0; a < 3; ++a)
+            if (!isfinite(force[a])) return fail(nullptr, LBM_EINVAL, "force must be finite");
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx;
+    if (!c) return fail(nullptr, LBM_ENOMEM, "out of host memory");
+    memset(c, 0, sizeof *c);
+    c->q = stencil;
+    c->st = d->storage;
+    c->cl = d->closure;
+    c->stream = (hipStream_t)d->stream;
+    c->ws = (char *)d->workspace;
+    c->ws_bytes = d->workspace_bytes;
+    c->partial = (double *)(c->ws + L.partial);
+    c->final_out = (double *)(c->ws + L.final_out);
+    c->mlp = (float *)(c->ws + L.mlp);
+    c->fallbacks = (unsigned long long *)(c->ws + L.fallback);
+    c->mask = d->use_flags ? (uint32_t *)(c->ws + L.mask) : nullptr;
+    c->state_bytes = L.pdf_bytes;
+
+    LatticeArgs &a = c->a;
+    memset(&a, 0, sizeof a);
+    a.pdf = c->ws + L.pdf;
+    a.mask = c->mask;
+    a.nx = d->nx;
+    a.ny = d->ny;
+    a.nz = d->nz;
+    a.n = (uint32_t)((uint64_t)d->nx * d->ny * d->nz);
+    a.plane = a.n;
+    for (int k = 0; k < 3; ++k) a.per[k] = d->bc[2 * k] == LBM_BC_PERIODIC;
+    a.any_vp = 0;
+    for (int f = 0; f < 6; ++f) {
+        a.bc[f] = d->bc[f];
+        if (d->bc[f] == LBM_BC_VELOCITY || d->bc[f] == LBM_BC_PRESSURE) a.any_vp = 1;
+        for (int k = 0; k < 3; ++k) a.ubc[f][k] = (float)d->u_bc[f][k];
+        a.rhobc[f] = (float)d->rho_bc[f];
+    }
+    for (int k = 0; k < 3; ++k) a.F[k] = force ? (float)force[k] : 0.f;
+    a.tau = (float)tau;
+    a.magic = (float)d->magic;
+    a.cs = (float)d->cs_smag;
+    a.omp = (float)(1.0 / tau);
+    a.omm = (float)(1.0 / (0.5 + d->magic / (tau - 0.5)));
+    a.mlp = c->mlp;
+    a.fallbacks = c->fallbacks;
+
+    c->nfluid = (int64_t)a.n;
+    hipError_t e = hipMemsetAsync(c->fallbacks, 0, sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess && c->mask) {
+        if (flags) {
+            int64_t solid = 0;
+            for (uint32_t k = 0; k < a.n; ++k) solid += flags[k] != 0;
+            c->nfluid -= solid;
+            // stage the flags in the (still undefined) population region
+            e = hipMemcpyAsync(a.pdf, flags, a.n, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = launch_build_mask(a, stencil, (const uint8_t *)a.pdf, c->mask, c->stream);
+        } else {
+            e = hipMemsetAsync(a.pdf, 0, a.n, c->stream);
+            if (e == hipSuccess) e = launch_build_mask(a, stencil, (const uint8_t *)a.pdf, c->mask, c->stream);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        hip_fail(nullptr, e, "lbm_create");
+        delete c;
+        return LBM_EDEVICE;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx *ctx)
+{
+    delete ctx;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err : g_err; }
+
+int lbm_init_equilibrium(lbm_ctx *c, const double *rho_dev, const double *u_dev)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (!rho_dev || !u_dev) return fail(c, LBM_EINVAL, "rho/u is NULL");
+    HIPCHECK(c, launch_init_eq(c->a, c->q, c->st, rho_dev, u_dev, c->stream), "init_equilibrium");
+    c->time = 0;
+    return LBM_OK;
+}
+
+int lbm_set_pdfs(lbm_ctx *c, const double *f_dev)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (!f_dev) return fail(c, LBM_EINVAL, "f is NULL");
+    HIPCHECK(c, launch_set_pdfs(c->a, c->q, c->st, f_dev, c->stream), "set_pdfs");
+    c->time = 0;
+    return LBM_OK;
+}
+
+int lbm_get_pdfs(lbm_ctx *c, double *f_dev)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (!f_dev) return fail(c, LBM_EINVAL, "f is NULL");
+    HIPCHECK(c, launch_get_pdfs(c->a, c->q, c->st, (int)(c->time & 1), f_dev, c->stream), "get_pdfs");
+    return LBM_OK;
+}
+
+int lbm_gather_pdfs(lbm_ctx *c, const int64_t *cells_dev, int64_t n, double *out_dev)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+    if (n > 0 && (!cells_dev || !out_dev)) return fail(c, LBM_EINVAL, "cells/out is NULL");
+    HIPCHECK(c, launch_gather(c->a, c->q, c->st, (int)(c->time & 1), cells_dev, n, out_dev, c->stream), "gather");
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t n)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (n < 0) return fail(c, LBM_EINVAL, "step count must be >= 0 (got %lld)", (long long)n);
+    if (c->cl == LBM_LES_MLP && !c->mlp_ready)
+        return fail(c, LBM_ESTATE, "MLP closure selected but lbm_set_closure_weights was not called");
+    for (int64_t k = 0; k < n; ++k) {
+        hipError_t e = launch_step(c->a, c->q, c->st, c->cl, (int)(c->time & 1), c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "stream_collide launch");
+        ++c->time;
+    }
+    return LBM_OK;
+}
+
+int64_t lbm_time(const lbm_ctx *c) { return c ? c->time : -1; }
+
+int lbm_moments(lbm_ctx *c, float *rho_dev, float *u_dev)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (!rho_dev || !u_dev) return fail(c, LBM_EINVAL, "rho/u is NULL");
+    HIPCHECK(c, launch_moments(c->a, c->q, c->st, (int)(c->time & 1), rho_dev, u_dev, c->stream), "moments");
+    return LBM_OK;
+}
+
+int lbm_totals(lbm_ctx *c, double *mass, double mom[3])
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (!mass || !mom) return fail(c, LBM_EINVAL, "mass/mom is NULL");
+    HIPCHECK(c, launch_totals(c->a, c->q, c->st, (int)(c->time & 1), c->partial, c->final_out, c->stream),
+             "totals");
+    double h[5];
+    HIPCHECK(c, hipMemcpyAsync(h, c->final_out, sizeof h, hipMemcpyDeviceToHost, c->stream), "totals copy");
+    HIPCHECK(c, hipStreamSynchronize(c->stream), "totals sync");
+    *mass = (double)c->nfluid + h[0];
+    mom[0] = h[1];
+    mom[1] = h[2];
+    mom[2] = h[3];
+    if (h[4] != 0.0 || !isfinite(h[0]) || !isfinite(h[1]) || !isfinite(h[2]) || !isfinite(h[3]))
+        return fail(c, LBM_ENONFINITE, "non-finite populations in %.0f fluid cells", h[4]);
+    return LBM_OK;
+}
+
+int lbm_state_bytes(const lbm_ctx *c, size_t *out)
+{
+    if (!c || !out) return fail(nullptr, LBM_EINVAL, "context/out is NULL");
+    *out = c->state_bytes;
+    return LBM_OK;
+}
+
+int lbm_save_state(lbm_ctx *c, void *dst_dev, int64_t *time)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (!dst_dev || !time) return fail(c, LBM_EINVAL, "dst/time is NULL");
+    HIPCHECK(c, hipMemcpyAsync(dst_dev, c->a.pdf, c->state_bytes, hipMemcpyDeviceToDevice, c->stream), "save_state");
+    *time = c->time;
+    return LBM_OK;
+}
+
+int lbm_load_state(lbm_ctx *c, const void *src_dev, int64_t time)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (!src_dev || time < 0) return fail(c, LBM_EINVAL, "src is NULL or time < 0");
+    HIPCHECK(c, hipMemcpyAsync(c->a.pdf, src_dev, c->state_bytes, hipMemcpyDeviceToDevice, c->stream), "load_state");
+    c->time = time;
+    return LBM_OK;
+}
+
+int lbm_set_closure_weights(lbm_ctx *c, const float *params, size_t n)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (!params || n != (size_t)(MLP_NPARAM + MLP_NNORM))
+        return fail(c, LBM_EINVAL, "closure weights: expected %d floats", MLP_NPARAM + MLP_NNORM);
+    for (size_t k = 0; k < n; ++k)
+        if (!isfinite(params[k])) return fail(c, LBM_EINVAL, "closure weight %zu is not finite", k);
+    for (int k = 0; k < 6; ++k)
+        if (!(params[MLP_NPARAM + 6 + k] > 0.f)) return fail(c, LBM_EINVAL, "sigma[%d] must be > 0", k);
+    HIPCHECK(c, hipMemcpyAsync(c->mlp, params, n * sizeof(float), hipMemcpyHostToDevice, c->stream), "weights");
+    HIPCHECK(c, hipStreamSynchronize(c->stream), "weights sync");
+    c->mlp_ready = 1;
+    return LBM_OK;
+}
+
+int lbm_closure_fallbacks(lbm_ctx *c, int64_t *count)
+{
+    if (!c || !count) return fail(c, LBM_EINVAL, "context/count is NULL");
+    unsigned long long h = 0;
+    HIPCHECK(c, hipMemcpyAsync(&h, c->fallbacks, sizeof h, hipMemcpyDeviceToHost, c->stream), "fallbacks copy");
+    HIPCHECK(c, hipStreamSynchronize(c->stream), "fallbacks sync");
+    HIPCHECK(c, hipMemsetAsync(c->fallbacks, 0, sizeof h, c->stream), "fallbacks reset");
+    *count = (int64_t)h;
+    return LBM_OK;
+}
+
+int lbm_box_filter4(int32_t nx, int32_t ny, int32_t nz, const float *rho_dev, const float *u_dev, float *out_dev,
+                    void *stream)
+{
+    if (nx < 4 || ny < 4 || nz < 4 || nx % 4 || ny % 4 || nz % 4)
+        return fail(nullptr, LBM_EINVAL, "box filter: sizes must be positive multiples of 4");
+    if ((uint64_t)nx * ny * nz >= (1ull << 31)) return fail(nullptr, LBM_ENOMEM, "box filter: too many cells");
+    if (!rho_dev || !u_dev || !out_dev) return fail(nullptr, LBM_EINVAL, "box filter: NULL pointer");
+    hipError_t e = launch_box_filter4(nx, ny, nz, rho_dev, u_dev, out_dev, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(nullptr, e, "box_filter4");
+}
+
+int lbm_closure_dataset(int32_t cx, int32_t cy, int32_t cz, const int32_t periodic[3], const float *filt_dev,
+                        double tau, double cs, float *x_dev, float *t_dev, void *stream)
+{
+    if (cx < 1 || cy < 1 || cz < 1) return fail(nullptr, LBM_EINVAL, "dataset: sizes must be >= 1");
+    if ((uint64_t)cx * cy * cz >= (1ull << 31)) return fail(nullptr, LBM_ENOMEM, "dataset: too many cells");
+    if (!periodic || !filt_dev || !x_dev || !t_dev) return fail(nullptr, LBM_EINVAL, "dataset: NULL pointer");
+    if (!(tau > 0.5) || !(cs >= 0.0)) return fail(nullptr, LBM_EINVAL, "dataset: tau must be > 1/2, cs >= 0");
+    int per[3] = {periodic[0] != 0, periodic[1] != 0, periodic[2] != 0};
+    hipError_t e = launch_closure_dataset(cx, cy, cz, per, filt_dev, (float)tau, (float)cs, x_dev, t_dev,
+                                          (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(nullptr, e, "closure_dataset");
+}
+
+int lbm_mlp_forward(const float *params_dev, const float *x_dev, int64_t n, float *y_dev, void *stream)
+{
+    if (n < 0) return fail(nullptr, LBM_EINVAL, "mlp_forward: n must be >= 0");
+    if (n > 0 && (!params_dev || !x_dev || !y_dev)) return fail(nullptr, LBM_EINVAL, "mlp_forward: NULL pointer");
+    hipError_t e = launch_mlp_forward(params_dev, x_dev, n, y_dev, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(nullptr, e, "mlp_forward");
+}
+
+size_t lbm_mlp_work_bytes(int64_t n) { return mlp_work_bytes(n < 0 ? 0 : n); }
+
+int lbm_mlp_loss_grad(const float *params_dev, const float *x_dev, const float *t_dev, int64_t n, float *grad_dev,
+                      float *loss_dev, void *work_dev, void *stream)
+{
+    if (n < 1) return fail(nullptr, LBM_EINVAL, "mlp_loss_grad: n must be >= 1");
+    if (!params_dev || !x_dev || !t_dev || !grad_dev || !loss_dev || !work_dev)
+        return fail(nullptr, LBM_EINVAL, "mlp_loss_grad: NULL pointer");
+    hipError_t e = launch_mlp_loss_grad(params_dev, x_dev, t_dev, n, grad_dev, loss_dev, work_dev, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(nullptr, e, "mlp_loss_grad");
+}
+
+int lbm_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int64_t step, double lr,
+                 double beta1, double beta2, double eps, void *stream)
+{
+    if (!params_dev || !grad_dev || !m_dev || !v_dev) return fail(nullptr, LBM_EINVAL, "mlp_adam: NULL pointer");
+    if (step < 1) return fail(nullptr, LBM_EINVAL, "mlp_adam: step is 1-based");
+    hipError_t e = launch_mlp_adam(params_dev, grad_dev, m_dev, v_dev, step, (float)lr, (float)beta1, (float)beta2,
+                                   (float)eps, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(nullptr, e, "mlp_adam");
+}
+
+int lbm_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, void *stream)
+{
+    if (!src_dev || !dst_dev) return fail(nullptr, LBM_EINVAL, "copy: NULL pointer");
+    if (bytes % 16) return fail(nullptr, LBM_EINVAL, "copy: bytes must be a multiple of 16");
+    hipError_t e = launch_copy(src_dev, dst_dev, bytes, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(nullptr, e, "stream_copy");
+}
+
+}  // extern "C"

@@ -1,0 +1,756 @@
+// lbm_kernels.hip -- fused in-place stream-collide kernels for gfx950.
+//
+// One population set lives in HBM as deviations d_i = f_i - w_i, structure
+// of arrays [q][z][y][x].  Streaming (the paper's Eq. (2)) and collision
+// (Eq. (1), read as TRT with Guo forcing) are fused into one kernel per time
+// step with the AA access pattern, an in-place scheme of the same family as
+// the Esoteric Twist the paper's LAGOON runs use (Section 5.2):
+//
+//   even step: cell x reads d_i from its own slot i, collides, and writes
+//              the post-collision value of direction i into its own slot
+//              opposite(i);
+//   odd step:  cell x reads d_i from slot opposite(i) of cell x - c_i,
+//              collides, and writes direction i into slot i of cell x + c_i.
+//
+// After an odd step the array holds the canonical post-stream state in the
+// natural slots; after an even step the post-collision values sit in
+// swapped slots of the emitting cell.  In both steps the set of slots a cell
+// reads equals the set it writes, so the update is race free in place.
+//
+// Walls: a link cut by a wall face or a solid neighbour is closed at write
+// time inside the emitting cell: the (possibly modified) value goes into
+// the cell's own slot opposite(i), which is exactly where that cell reads
+// its returning population next step.  Velocity and pressure faces modify
+// the value there with the emitting cell's own velocity.
+//
+// The kernel is bound by HBM bandwidth (every population is read once and
+// written once per step); no matrix cores are used here.  All arithmetic is
+// FP32 on deviations, which keeps small forcing increments above the FP32
+// rounding of w_i.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "internal.h"
+#include "mlp_wave.h"
+#include "stencil.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// storage formats
+// ---------------------------------------------------------------------------
+template <int ST>
+struct Store;
+
+template <>
+struct Store<ST_F32> {
+    using T = float;
+    __device__ static float ld(const T *p) { return *p; }
+    __device__ static void st(T *p, float v) { *p = v; }
+    __device__ static T cvt(float v) { return v; }
+};
+
+template <>
+struct Store<ST_F16> {
+    using T = _Float16;
+    __device__ static float ld(const T *p) { return (float)*p; }
+    __device__ static void st(T *p, float v) { *p = (_Float16)v; }
+    __device__ static T cvt(float v) { return (_Float16)v; }
+};
+
+// bfloat16 as raw bits: widen by a shift, narrow with round-to-nearest-even
+__device__ inline uint16_t f32_to_bf16_rne(float v)
+{
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <>
+struct Store<ST_BF16> {
+    using T = uint16_t;
+    __device__ static float ld(const T *p) { return __uint_as_float((uint32_t)*p << 16); }
+    __device__ static void st(T *p, float v) { *p = f32_to_bf16_rne(v); }
+    __device__ static T cvt(float v) { return f32_to_bf16_rne(v); }
+};
+
+// ---------------------------------------------------------------------------
+// cell geometry
+// ---------------------------------------------------------------------------
+struct Geom {
+    int x, y, z;
+    uint32_t c;
+    int xm, xp, ym, yp, zm, zp;    // wrapped neighbour coordinates
+    bool cxl, cxh, cyl, cyh, czl, czh;  // link through that face is cut by a non-periodic face
+};
+
+__device__ inline Geom make_geom(const LatticeArgs &a, int x, int y, int z)
+{
+    Geom g;
+    g.x = x;
+    g.y = y;
+    g.z = z;
+    g.c = ((uint32_t)z * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx + (uint32_t)x;
+    g.xm = x == 0 ? a.nx - 1 : x - 1;
+    g.xp = x == a.nx - 1 ? 0 : x + 1;
+    g.ym = y == 0 ? a.ny - 1 : y - 1;
+    g.yp = y == a.ny - 1 ? 0 : y + 1;
+    g.zm = z == 0 ? a.nz - 1 : z - 1;
+    g.zp = z == a.nz - 1 ? 0 : z + 1;
+    g.cxl = !a.per[0] && x == 0;
+    g.cxh = !a.per[0] && x == a.nx - 1;
+    g.cyl = !a.per[1] && y == 0;
+    g.cyh = !a.per[1] && y == a.ny - 1;
+    g.czl = !a.per[2] && z == 0;
+    g.czh = !a.per[2] && z == a.nz - 1;
+    return g;
+}
+
+// index of the neighbour at offset (dx, dy, dz), periodic wrap
+__device__ inline uint32_t nbr(const LatticeArgs &a, const Geom &g, int dx, int dy, int dz)
+{
+    const int xx = dx < 0 ? g.xm : (dx > 0 ? g.xp : g.x);
+    const int yy = dy < 0 ? g.ym : (dy > 0 ? g.yp : g.y);
+    const int zz = dz < 0 ? g.zm : (dz > 0 ? g.zp : g.z);
+    return ((uint32_t)zz * (uint32_t)a.ny + (uint32_t)yy) * (uint32_t)a.nx + (uint32_t)xx;
+}
+
+// does the link from this cell along (dx, dy, dz) leave through a non-periodic face?
+__device__ inline bool face_cut(const Geom &g, int dx, int dy, int dz)
+{
+    return (dx < 0 && g.cxl) || (dx > 0 && g.cxh) || (dy < 0 && g.cyl) || (dy > 0 && g.cyh) ||
+           (dz < 0 && g.czl) || (dz > 0 && g.czh);
+}
+
+// Face that decides a cut link along (dx, dy, dz): among the crossed
+// non-periodic faces the first of no-slip, velocity, pressure (lowest face
+// index among equals).  Returns -1 when no face is crossed.
+__device__ inline int deciding_face(const LatticeArgs &a, const Geom &g, int dx, int dy, int dz)
+{
+    int best = -1, rank = 0;
+    const bool cross[6] = {dx < 0 && g.cxl, dx > 0 && g.cxh, dy < 0 && g.cyl,
+                           dy > 0 && g.cyh, dz < 0 && g.czl, dz > 0 && g.czh};
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        if (!cross[f]) continue;
+        const int k = a.bc[f];
+        const int r = k == BC_NOSLIP ? 3 : (k == BC_VELOCITY ? 2 : (k == BC_PRESSURE ? 1 : 0));
+        if (r > rank) {
+            rank = r;
+            best = f;
+        }
+    }
+    return best;
+}
+
+// ---------------------------------------------------------------------------
+// canonical read (shared by the step kernel and every state reader)
+// ---------------------------------------------------------------------------
+template <int Q, int ST>
+__device__ inline void load_canonical(const LatticeArgs &a, const Geom &g, uint32_t m, int odd, float (&d)[Q])
+{
+    using S = Store<ST>;
+    const typename S::T *A = (const typename S::T *)a.pdf;
+    const uint64_t N = a.plane;
+    if (!odd) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = S::ld(A + (uint64_t)i * N + g.c);
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
+            // source x - c_i; blocked when that link is cut (mask bit of opposite(i))
+            const bool cut = face_cut(g, -dx, -dy, -dz) || ((m >> opp(i)) & 1u);
+            const uint64_t own = (uint64_t)i * N + g.c;
+            const uint64_t src = (uint64_t)opp(i) * N + nbr(a, g, -dx, -dy, -dz);
+            d[i] = S::ld(A + (cut ? own : src));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// collision: TRT + Guo on deviations, optional Smagorinsky relaxation time
+// ---------------------------------------------------------------------------
+struct Macro {
+    float rho, ux, uy, uz;
+};
+
+template <int Q>
+__device__ inline Macro moments(const LatticeArgs &a, const float (&d)[Q], float &drho)
+{
+    float s = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        s += d[i];
+        if (cdir(i, 0)) jx += cdir(i, 0) > 0 ? d[i] : -d[i];
+        if (cdir(i, 1)) jy += cdir(i, 1) > 0 ? d[i] : -d[i];
+        if (cdir(i, 2)) jz += cdir(i, 2) > 0 ? d[i] : -d[i];
+    }
+    drho = s;
+    Macro M;
+    M.rho = 1.f + s;
+    const float ir = 1.f / M.rho;
+    M.ux = (jx + 0.5f * a.F[0]) * ir;
+    M.uy = (jy + 0.5f * a.F[1]) * ir;
+    M.uz = (jz + 0.5f * a.F[2]) * ir;
+    return M;
+}
+
+// Non-equilibrium momentum flux with the forcing correction,
+// P_c = sum_i c_i c_i (f_i - f_i^eq) + (u F + F u)/2, packed xx,yy,zz,xy,xz,yz.
+// With deviations, sum_i c c f^eq - sum_i c c w = drho/3 I + rho u u.
+template <int Q>
+__device__ inline void noneq_flux(const LatticeArgs &a, const float (&d)[Q], float drho, const Macro &M,
+                                  float (&P)[6])
+{
+    float pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pxz = 0.f, pyz = 0.f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int cx = cdir(i, 0), cy = cdir(i, 1), cz = cdir(i, 2);
+        if (cx) pxx += d[i];
+        if (cy) pyy += d[i];
+        if (cz) pzz += d[i];
+        if (cx * cy) pxy += cx * cy > 0 ? d[i] : -d[i];
+        if (cx * cz) pxz += cx * cz > 0 ? d[i] : -d[i];
+        if (cy * cz) pyz += cy * cz > 0 ? d[i] : -d[i];
+    }
+    const float third = drho * (1.f / 3.f);
+    const float F0 = a.F[0], F1 = a.F[1], F2 = a.F[2];
+    P[0] = pxx - third - M.rho * M.ux * M.ux + M.ux * F0;
+    P[1] = pyy - third - M.rho * M.uy * M.uy + M.uy * F1;
+    P[2] = pzz - third - M.rho * M.uz * M.uz + M.uz * F2;
+    P[3] = pxy - M.rho * M.ux * M.uy + 0.5f * (M.ux * F1 + F0 * M.uy);
+    P[4] = pxz - M.rho * M.ux * M.uz + 0.5f * (M.ux * F2 + F0 * M.uz);
+    P[5] = pyz - M.rho * M.uy * M.uz + 0.5f * (M.uy * F2 + F1 * M.uz);
+}
+
+__device__ inline float flux_norm(const float (&P)[6])
+{
+    return sqrtf(P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + 2.f * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]));
+}
+
+// Hou et al. (1996) Smagorinsky relaxation time from |P_c|:
+// tau_s = (tau + sqrt(tau^2 + a)) / 2 with a = 18 sqrt(2) Cs^2 |P_c| / rho.
+// Returned as the excess tau_s - tau = (a/2) / (sqrt(tau^2 + a) + tau), which
+// has no cancellation in FP32 when a << tau^2.
+__device__ inline float smag_excess(float tau, float cs, float Qn, float rho)
+{
+    const float a = 18.f * 1.41421356237f * cs * cs * Qn / rho;
+    return 0.5f * a / (sqrtf(tau * tau + a) + tau);
+}
+
+template <int Q>
+__device__ inline void trt_collide(const LatticeArgs &a, float (&d)[Q], float drho, const Macro &M, float wp,
+                                   float wm)
+{
+    const float F0 = a.F[0], F1 = a.F[1], F2 = a.F[2];
+    const float usq = M.ux * M.ux + M.uy * M.uy + M.uz * M.uz;
+    const float uF = M.ux * F0 + M.uy * F1 + M.uz * F2;
+    const float kp = 1.f - 0.5f * wp, km = 1.f - 0.5f * wm;
+    const float base = drho - 1.5f * M.rho * usq;  // shared part of the symmetric equilibrium
+    {
+        constexpr float w0 = (float)wgt<Q>(0);
+        const float deq = w0 * base;
+        const float S = w0 * (-3.f * uF);
+        d[0] = d[0] - wp * (d[0] - deq) + kp * S;
+    }
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+        const int cx = cdir(i, 0), cy = cdir(i, 1), cz = cdir(i, 2);
+        const float w = (float)wgt<Q>(i);
+        const float cu = cx * M.ux + cy * M.uy + cz * M.uz;
+        const float cF = cx * F0 + cy * F1 + cz * F2;
+        const float deqp = w * (base + 4.5f * M.rho * cu * cu);
+        const float eqm = 3.f * w * M.rho * cu;
+        const float Sp = w * (9.f * cu * cF - 3.f * uF);
+        const float Sm = 3.f * w * cF;
+        const float dp = 0.5f * (d[i] + d[i + 1]);
+        const float dm = 0.5f * (d[i] - d[i + 1]);
+        const float A = -wp * (dp - deqp) + kp * Sp;
+        const float B = -wm * (dm - eqm) + km * Sm;
+        d[i] = d[i] + A + B;
+        d[i + 1] = d[i + 1] + A - B;
+    }
+}
+
+// Value a cut link returns to its own cell (deviation form).
+template <int Q>
+__device__ inline float wall_value(const LatticeArgs &a, int face, int i, float v, const Macro &M)
+{
+    if (face < 0) return v;  // solid neighbour: plain bounce-back
+    const int k = a.bc[face];
+    const float w = (float)wgt<Q>(i);
+    const int cx = cdir(i, 0), cy = cdir(i, 1), cz = cdir(i, 2);
+    if (k == BC_VELOCITY) {
+        const float cuw = cx * a.ubc[face][0] + cy * a.ubc[face][1] + cz * a.ubc[face][2];
+        return v - 6.f * w * a.rhobc[face] * cuw;
+    }
+    if (k == BC_PRESSURE) {
+        const float cu = cx * M.ux + cy * M.uy + cz * M.uz;
+        const float usq = M.ux * M.ux + M.uy * M.uy + M.uz * M.uz;
+        const float rw = a.rhobc[face];
+        return -v + 2.f * w * (rw - 1.f + rw * (4.5f * cu * cu - 1.5f * usq));
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// the fused stream-collide kernel
+// ---------------------------------------------------------------------------
+template <int Q, int ST, int CL, bool MASK>
+__global__ void __launch_bounds__(256) k_stream_collide(LatticeArgs a, int odd)
+{
+    using S = Store<ST>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    bool active = x < a.nx && y < a.ny;
+    // The learned closure runs on the matrix cores across the whole
+    // wavefront, so with it every lane stays to the end; otherwise lanes
+    // outside the domain or on solid cells leave at once.
+    if constexpr (CL != CL_MLP) {
+        if (!active) return;
+    }
+    const Geom g = make_geom(a, active ? x : 0, active ? y : 0, z);
+    uint32_t m = 0;
+    if constexpr (MASK) {
+        m = active ? a.mask[g.c] : 0u;
+        if (m & SELF_SOLID) {
+            if constexpr (CL != CL_MLP) return;
+            active = false;
+        }
+    }
+    float d[Q];
+    if constexpr (CL == CL_MLP) {
+        if (active) {
+            load_canonical<Q, ST>(a, g, m, odd, d);
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[i] = 0.f;
+        }
+    } else {
+        load_canonical<Q, ST>(a, g, m, odd, d);
+    }
+
+    float drho;
+    const Macro M = moments<Q>(a, d, drho);
+    float wp = a.omp, wm = a.omm;
+    if constexpr (CL == CL_SMAG || CL == CL_MLP) {
+        float P[6];
+        noneq_flux<Q>(a, d, drho, M, P);
+        const float excess = smag_excess(a.tau, a.cs, flux_norm(P), M.rho);
+        const float tsm = a.tau + excess;
+        float tt = tsm;
+        if constexpr (CL == CL_MLP) {
+            const float ir = 1.f / M.rho;
+            float Pn[6], xf[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Pn[k] = P[k] * ir;
+            closure_features(Pn, M.rho, a.tau, excess, xf);
+            const int lane = (threadIdx.y * blockDim.x + threadIdx.x) & 63;
+            const bool inside = features_in_range(a.mlp, xf);
+            float xin[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) xin[k] = inside ? xf[k] : a.mlp[P_MU + k];
+            const float dtau = softplus_f(mlp_forward_wave(a.mlp, xin, lane));
+            const bool use = inside && isfinite(dtau);
+            tt = use ? a.tau + dtau : tsm;
+            const uint64_t fb = __ballot(active && !use);
+            if (lane == 0 && fb) atomicAdd(a.fallbacks, (unsigned long long)__popcll(fb));
+        }
+        wp = 1.f / tt;
+        wm = 1.f / (0.5f + a.magic / (tt - 0.5f));
+    }
+    trt_collide<Q>(a, d, drho, M, wp, wm);
+    if constexpr (CL == CL_MLP) {
+        if (!active) return;
+    }
+
+    typename S::T *A = (typename S::T *)a.pdf;
+    const uint64_t N = a.plane;
+    if (!odd) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            float v = d[i];
+            if (a.any_vp) {
+                const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
+                if (face_cut(g, dx, dy, dz)) v = wall_value<Q>(a, deciding_face(a, g, dx, dy, dz), i, v, M);
+            }
+            S::st(A + (uint64_t)opp(i) * N + g.c, v);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
+            const bool fcut = face_cut(g, dx, dy, dz);
+            const bool cut = fcut || ((m >> i) & 1u);
+            float v = d[i];
+            if (a.any_vp && fcut) v = wall_value<Q>(a, deciding_face(a, g, dx, dy, dz), i, v, M);
+            const uint64_t own = (uint64_t)opp(i) * N + g.c;
+            const uint64_t dst = (uint64_t)i * N + nbr(a, g, dx, dy, dz);
+            S::st(A + (cut ? own : dst), v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// set-up and state kernels
+// ---------------------------------------------------------------------------
+template <int Q>
+__global__ void __launch_bounds__(256) k_build_mask(LatticeArgs a, const uint8_t *flags, uint32_t *mask)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const Geom g = make_geom(a, x, y, z);
+    uint32_t m = flags[g.c] ? SELF_SOLID : 0u;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
+        if (!face_cut(g, dx, dy, dz) && flags[nbr(a, g, dx, dy, dz)]) m |= 1u << i;
+    }
+    mask[g.c] = m;
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_init_eq(LatticeArgs a, const double *rho, const double *u)
+{
+    using S = Store<ST>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const Geom g = make_geom(a, x, y, z);
+    const bool solid = a.mask && (a.mask[g.c] & SELF_SOLID);
+    const double r = rho[g.c], ux = u[g.c], uy = u[a.plane + g.c], uz = u[2 * a.plane + g.c];
+    const double usq = ux * ux + uy * uy + uz * uz;
+    typename S::T *A = (typename S::T *)a.pdf;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double cu = cdir(i, 0) * ux + cdir(i, 1) * uy + cdir(i, 2) * uz;
+        const double dev = wgt<Q>(i) * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
+        A[(uint64_t)i * a.plane + g.c] = S::cvt(solid ? 0.f : (float)dev);
+    }
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_set_pdfs(LatticeArgs a, const double *f)
+{
+    using S = Store<ST>;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const Geom g = make_geom(a, x, y, z);
+    typename S::T *A = (typename S::T *)a.pdf;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const uint64_t k = (uint64_t)i * a.plane + g.c;
+        A[k] = S::cvt((float)(f[k] - wgt<Q>(i)));
+    }
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_get_pdfs(LatticeArgs a, int odd, double *f)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const Geom g = make_geom(a, x, y, z);
+    const uint32_t m = a.mask ? a.mask[g.c] : 0u;
+    float d[Q];
+    if (m & SELF_SOLID) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = 0.f;
+    } else {
+        load_canonical<Q, ST>(a, g, m, odd, d);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[(uint64_t)i * a.plane + g.c] = wgt<Q>(i) + (double)d[i];
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_gather(LatticeArgs a, int odd, const int64_t *cells, int64_t ncell,
+                                                double *out)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= ncell) return;
+    const int64_t c = cells[r];
+    if (c < 0 || c >= (int64_t)a.n) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) out[r * Q + i] = __builtin_nan("");
+        return;
+    }
+    const int x = (int)(c % a.nx), y = (int)((c / a.nx) % a.ny), z = (int)(c / ((int64_t)a.nx * a.ny));
+    const Geom g = make_geom(a, x, y, z);
+    const uint32_t m = a.mask ? a.mask[g.c] : 0u;
+    float d[Q];
+    if (m & SELF_SOLID) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = 0.f;
+    } else {
+        load_canonical<Q, ST>(a, g, m, odd, d);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[r * Q + i] = wgt<Q>(i) + (double)d[i];
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_moments(LatticeArgs a, int odd, float *rho, float *u)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const Geom g = make_geom(a, x, y, z);
+    const uint32_t m = a.mask ? a.mask[g.c] : 0u;
+    if (m & SELF_SOLID) {
+        rho[g.c] = 1.f;
+        u[g.c] = u[a.plane + g.c] = u[2 * a.plane + g.c] = 0.f;
+        return;
+    }
+    float d[Q];
+    load_canonical<Q, ST>(a, g, m, odd, d);
+    float drho;
+    const Macro M = moments<Q>(a, d, drho);
+    rho[g.c] = M.rho;
+    u[g.c] = M.ux;
+    u[a.plane + g.c] = M.uy;
+    u[2 * a.plane + g.c] = M.uz;
+}
+
+// Deterministic FP64 totals: each block owns a fixed slice of cells and
+// reduces it in a fixed order (lanes, then wavefronts); a second kernel sums
+// the block partials in index order.
+constexpr int TOT_BLOCKS = 1024;
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int Q, int ST>
+__global__ void __launch_bounds__(256) k_totals(LatticeArgs a, int odd, double *partial)
+{
+    double acc[5] = {0, 0, 0, 0, 0};
+    const uint32_t per_block = (a.n + TOT_BLOCKS - 1) / TOT_BLOCKS;
+    const uint32_t lo = blockIdx.x * per_block;
+    const uint32_t hi = min(a.n, lo + per_block);
+    for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
+        const int x = (int)(c % (uint32_t)a.nx);
+        const int y = (int)((c / (uint32_t)a.nx) % (uint32_t)a.ny);
+        const int z = (int)(c / ((uint32_t)a.nx * (uint32_t)a.ny));
+        const Geom g = make_geom(a, x, y, z);
+        const uint32_t m = a.mask ? a.mask[g.c] : 0u;
+        if (m & SELF_SOLID) continue;
+        float d[Q];
+        load_canonical<Q, ST>(a, g, m, odd, d);
+        float s = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            s += d[i];
+            jx += cdir(i, 0) * d[i];
+            jy += cdir(i, 1) * d[i];
+            jz += cdir(i, 2) * d[i];
+        }
+        acc[0] += (double)s;
+        acc[1] += (double)jx;
+        acc[2] += (double)jy;
+        acc[3] += (double)jz;
+        acc[4] += isfinite(s) ? 0.0 : 1.0;
+    }
+    __shared__ double red[4][5];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double v = wave_sum(acc[k]);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[w][threadIdx.x];
+        partial[blockIdx.x * 5 + threadIdx.x] = v;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_totals_final(const double *partial, double *out)
+{
+    const int k = threadIdx.x;
+    if (k >= 5) return;
+    double v = 0.0;
+    for (int b = 0; b < TOT_BLOCKS; ++b) v += partial[b * 5 + k];
+    out[k] = v;
+}
+
+__global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ src, float4 *__restrict__ dst, size_t n)
+{
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        dst[k] = src[k];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+Launch lattice_launch(const LatticeArgs &a)
+{
+    // Block = 256 threads: BX cells along x (a row segment) times BY rows.
+    // Whole rows per block keep the +-1 shifted reads of the odd step inside
+    // one workgroup (no cache line shared between blocks within a row).
+    int bx = 256;
+    if (a.nx % 256 != 0) {
+        bx = 32;
+        for (int c : {128, 64}) {
+            if (a.nx % c == 0) {
+                bx = c;
+                break;
+            }
+        }
+        if (a.nx < 32) bx = 32;
+        else if (a.nx % 32 != 0) bx = 64;
+    }
+    const int by = 256 / bx;
+    Launch L;
+    L.block = dim3(bx, by, 1);
+    L.grid = dim3((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, a.nz);
+    return L;
+}
+
+hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, uint32_t *mask, hipStream_t s)
+{
+    const Launch L = lattice_launch(a);
+    if (q == 19)
+        k_build_mask<19><<<L.grid, L.block, 0, s>>>(a, flags, mask);
+    else
+        k_build_mask<27><<<L.grid, L.block, 0, s>>>(a, flags, mask);
+    return hipGetLastError();
+}
+
+template <int Q, int ST>
+static hipError_t step_q_st(const LatticeArgs &a, int cl, int odd, hipStream_t s)
+{
+    const Launch L = lattice_launch(a);
+    const bool mk = a.mask != nullptr;
+    if (cl == CL_NONE) {
+        if (mk)
+            k_stream_collide<Q, ST, CL_NONE, true><<<L.grid, L.block, 0, s>>>(a, odd);
+        else
+            k_stream_collide<Q, ST, CL_NONE, false><<<L.grid, L.block, 0, s>>>(a, odd);
+    } else if (cl == CL_SMAG) {
+        if (mk)
+            k_stream_collide<Q, ST, CL_SMAG, true><<<L.grid, L.block, 0, s>>>(a, odd);
+        else
+            k_stream_collide<Q, ST, CL_SMAG, false><<<L.grid, L.block, 0, s>>>(a, odd);
+    } else {
+        if (mk)
+            k_stream_collide<Q, ST, CL_MLP, true><<<L.grid, L.block, 0, s>>>(a, odd);
+        else
+            k_stream_collide<Q, ST, CL_MLP, false><<<L.grid, L.block, 0, s>>>(a, odd);
+    }
+    return hipGetLastError();
+}
+
+// Calls f(integral_constant<Q>, integral_constant<ST>) for the runtime pair.
+template <class Fn>
+static hipError_t dispatch(int q, int st, Fn &&f)
+{
+    using I19 = std::integral_constant<int, 19>;
+    using I27 = std::integral_constant<int, 27>;
+    using S0 = std::integral_constant<int, ST_F32>;
+    using S1 = std::integral_constant<int, ST_F16>;
+    using S2 = std::integral_constant<int, ST_BF16>;
+    if (q == 19) {
+        if (st == ST_F32) return f(I19{}, S0{});
+        if (st == ST_F16) return f(I19{}, S1{});
+        return f(I19{}, S2{});
+    }
+    if (st == ST_F32) return f(I27{}, S0{});
+    if (st == ST_F16) return f(I27{}, S1{});
+    return f(I27{}, S2{});
+}
+
+hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int odd, hipStream_t s)
+{
+    return dispatch(q, st, [&](auto Q, auto ST) { return step_q_st<Q.value, ST.value>(a, cl, odd, s); });
+}
+
+hipError_t launch_init_eq(const LatticeArgs &a, int q, int st, const double *rho, const double *u, hipStream_t s)
+{
+    const Launch L = lattice_launch(a);
+    return dispatch(q, st, [&](auto Q, auto ST) {
+        k_init_eq<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, rho, u);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_set_pdfs(const LatticeArgs &a, int q, int st, const double *f, hipStream_t s)
+{
+    const Launch L = lattice_launch(a);
+    return dispatch(q, st, [&](auto Q, auto ST) {
+        k_set_pdfs<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, f);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_get_pdfs(const LatticeArgs &a, int q, int st, int odd, double *f, hipStream_t s)
+{
+    const Launch L = lattice_launch(a);
+    return dispatch(q, st, [&](auto Q, auto ST) {
+        k_get_pdfs<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, odd, f);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_gather(const LatticeArgs &a, int q, int st, int odd, const int64_t *cells, int64_t ncell,
+                         double *out, hipStream_t s)
+{
+    if (ncell <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((ncell + 255) / 256)), block(256);
+    return dispatch(q, st, [&](auto Q, auto ST) {
+        k_gather<Q.value, ST.value><<<grid, block, 0, s>>>(a, odd, cells, ncell, out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_moments(const LatticeArgs &a, int q, int st, int odd, float *rho, float *u, hipStream_t s)
+{
+    const Launch L = lattice_launch(a);
+    return dispatch(q, st, [&](auto Q, auto ST) {
+        k_moments<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, odd, rho, u);
+        return hipGetLastError();
+    });
+}
+
+int totals_blocks() { return TOT_BLOCKS; }
+
+hipError_t launch_totals(const LatticeArgs &a, int q, int st, int odd, double *partial, double *final_out,
+                         hipStream_t s)
+{
+    hipError_t e = dispatch(q, st, [&](auto Q, auto ST) {
+        k_totals<Q.value, ST.value><<<TOT_BLOCKS, 256, 0, s>>>(a, odd, partial);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    k_totals_final<<<1, 64, 0, s>>>(partial, final_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 256 * 8 * 16);
+    if (n == 0) return hipSuccess;
+    k_copy<<<(unsigned)blocks, 256, 0, s>>>((const float4 *)src, (float4 *)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,111 @@
+"""The C-ABI library loads, exports every function declared in include/lbm.h,
+and rejects invalid arguments before touching the GPU (no device calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2305_09910_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_2305_09910_amd import build
+        build.build()
+    return lbm.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(lbm.EXPORTED) == names
+
+
+def test_domain_defaults(L):
+    d = lbm.make_domain((8, 4, 2))
+    assert list(d.bc) == [0] * 6 and list(d.rho_bc) == [1.0] * 6
+    assert d.magic == 3 / 16 and d.cs_smag == 0.1 and d.storage == 0 and d.closure == 0
+
+
+def test_workspace_bytes_scales_with_storage(L):
+    b32 = lbm.workspace_bytes(lbm.make_domain((64, 32, 16), storage="f32"), 19)
+    b16 = lbm.workspace_bytes(lbm.make_domain((64, 32, 16), storage="f16"), 19)
+    n = 64 * 32 * 16
+    assert b32 >= 19 * 4 * n and b16 >= 19 * 2 * n and b32 - b16 == 19 * 2 * n
+    bf = lbm.workspace_bytes(lbm.make_domain((64, 32, 16), use_flags=True), 27)
+    assert bf >= 27 * 4 * n + 4 * n
+
+
+@pytest.mark.parametrize("kw,q", [
+    (dict(shape=(0, 4, 4)), 19),
+    (dict(shape=(4, 4, 4)), 15),
+    (dict(shape=(4, 4, 4), storage=7), 19),
+    (dict(shape=(4, 4, 4), closure=5), 19),
+])
+def test_workspace_bytes_rejects(L, kw, q):
+    d = lbm.make_domain(**kw)
+    out = ctypes.c_size_t(0)
+    assert L.lbm_workspace_bytes(ctypes.byref(d), q, ctypes.byref(out)) == lbm.LBM_EINVAL
+    assert L.lbm_last_error(None)
+
+
+def test_too_many_cells_is_enomem(L):
+    d = lbm.make_domain((2048, 1024, 1024))
+    out = ctypes.c_size_t(0)
+    assert L.lbm_workspace_bytes(ctypes.byref(d), 19, ctypes.byref(out)) == lbm.LBM_ENOMEM
+
+
+def _create(L, d, q=19, tau=0.6, flags=None):
+    F = (ctypes.c_double * 3)(0, 0, 0)
+    h = ctypes.c_void_p(0)
+    rc = L.lbm_create(ctypes.byref(d), q, flags, tau, F, ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("case", ["tau", "pairing", "bcenum", "null_ws", "small_ws", "align", "flags"])
+def test_create_rejects_before_device(L, case):
+    d = lbm.make_domain((8, 8, 8))
+    need = lbm.workspace_bytes(d, 19)
+    d.workspace = 0x100000
+    d.workspace_bytes = need
+    tau = 0.6
+    flags = None
+    if case == "tau":
+        tau = 0.5
+    elif case == "pairing":
+        d.bc[2] = 1  # -y no-slip, +y periodic
+    elif case == "bcenum":
+        d.bc[0] = d.bc[1] = 9
+    elif case == "null_ws":
+        d.workspace = None
+    elif case == "small_ws":
+        d.workspace_bytes = need - 1
+    elif case == "align":
+        d.workspace = 0x100010
+    elif case == "flags":
+        buf = (ctypes.c_uint8 * 512)()
+        flags = ctypes.cast(buf, ctypes.c_void_p)
+    rc, h = _create(L, d, tau=tau, flags=flags)
+    assert rc == lbm.LBM_EINVAL and not h.value
+    assert len(L.lbm_last_error(None)) > 0
+
+
+def test_free_functions_reject(L):
+    assert L.lbm_box_filter4(6, 8, 8, 1, 1, 1, None) == lbm.LBM_EINVAL
+    assert L.lbm_stream_copy(0x1000, 0x2000, 15, None) == lbm.LBM_EINVAL
+    assert L.lbm_mlp_forward(None, None, -1, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_mlp_adam(0x1000, 0x1000, 0x1000, 0x1000, 0, 1e-3, 0.9, 0.999, 1e-8, None) == lbm.LBM_EINVAL
+    per = (ctypes.c_int32 * 3)(1, 0, 1)
+    assert L.lbm_closure_dataset(4, 4, 4, per, 0x1000, 0.5, 0.1, 0x1000, 0x1000, None) == lbm.LBM_EINVAL

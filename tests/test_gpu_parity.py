@@ -1,0 +1,296 @@
+"""GPU (HIP, through the C ABI) versus the FP64 oracle, element by element.
+
+Tolerances: FP32 storage must stay within 1e-5 maximum relative population
+error of the oracle after 1000 steps (max over fluid cells and directions of
+|f_gpu - f_orc| / |f_orc|).  FP16/BF16 storage bounds are derived in the
+tests that use them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_09910_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_09910_amd import lbm
+    lbm.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _lbm():
+    from paper_2305_09910_amd import lbm
+    return lbm
+
+
+BCS = {"periodic": oracle.BC_PERIODIC, "noslip": oracle.BC_NOSLIP, "velocity": oracle.BC_VELOCITY,
+       "pressure": oracle.BC_PRESSURE}
+
+
+def pair(shape, q=19, tau=0.6, force=(0, 0, 0), bc=("periodic",) * 6, u_bc=None, rho_bc=None, solid=None,
+         storage="f32", closure="none", cs=0.1, magic=3 / 16):
+    """A GPU lattice and an oracle simulation with identical parameters."""
+    print(f"[case] q={q} shape={shape} bc={bc} storage={storage} closure={closure}", flush=True)
+    g = _lbm().Lattice(shape, q=q, tau=tau, force=force, bc=bc, u_bc=u_bc, rho_bc=rho_bc, solid=solid,
+                       storage=storage, closure=closure, cs=cs, magic=magic)
+    cl = {"none": oracle.CL_NONE, "smagorinsky": oracle.CL_SMAG, "mlp": oracle.CL_MLP}[closure]
+    o = oracle.Sim(q, shape, bc=tuple(BCS[b] for b in bc), tau=tau, magic=magic, force=force, u_bc=u_bc,
+                   rho_bc=rho_bc, solid=solid, closure=cl, cs=cs)
+    return g, o
+
+
+def max_rel(g_pdfs, o_pdfs, solid=None):
+    a = g_pdfs.detach().cpu().numpy() if hasattr(g_pdfs, "detach") else g_pdfs
+    b = o_pdfs
+    err = np.abs(a - b) / np.abs(b)
+    if solid is not None:
+        err = err[:, solid.reshape(b.shape[1:]) == 0]
+    return float(err.max())
+
+
+# ---------------------------------------------------------------------------
+# FP32 parity
+# ---------------------------------------------------------------------------
+def test_taylor_green_32cubed_1000_steps():
+    """Taylor-Green vortex, D3Q19 TRT, 32^3 periodic, nu = 0.01, u0 = 0.05."""
+    n = 32
+    g, o = pair((n, n, n), tau=3 * 0.01 + 0.5)
+    rho, u = inputs.taylor_green(n, n, n, 0.05)
+    g.init_equilibrium(rho, u)
+    o.init_equilibrium(rho, u)
+    g.step(1000)
+    o.step(1000)
+    err = max_rel(g.get_pdfs(), o.get_pdfs())
+    print("TGV max rel err", err)
+    assert err <= TOL32
+    # mass and momentum totals agree (FP64 reductions on the GPU)
+    mg, pg = g.totals()
+    mo, po = o.totals()
+    assert abs(mg - mo) / mo < 1e-7
+    # FP32 collisions conserve momentum to the unit roundoff 2^-24 of each
+    # cell's momentum (|rho u| <= u0); bound the sum over N cells by N u0 2^-23
+    assert np.abs(pg - po).max() < n ** 3 * 0.05 * 2.0 ** -23
+    # decay rate of the velocity amplitude exp(-2 nu k^2 t)
+    _, ug = g.moments()
+    k = 2 * math.pi / n
+    x = np.arange(n)[None, None, :]
+    y = np.arange(n)[None, :, None]
+    mode = np.broadcast_to(np.cos(k * x) * np.sin(k * y), (n, n, n))
+    amp = float((ug[0].cpu().numpy() * mode).sum() / (mode * mode).sum())
+    expect = 0.05 * math.exp(-2 * 0.01 * k * k * 1000)
+    assert abs(amp / expect - 1) < 0.01
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("nsteps", [1, 2, 3, 10, 11])
+def test_parity_aware_state_after_odd_and_even_steps(q, nsteps):
+    shape = (16, 12, 8)
+    solid = np.zeros(shape[::-1], np.uint8)
+    solid[3:5, 4:7, 5:9] = 1
+    uw = np.zeros((6, 3))
+    uw[0] = (0.03, 0.004, -0.002)
+    g, o = pair(shape, q=q, tau=0.57, force=(2e-5, -1e-5, 3e-6),
+                bc=("velocity", "pressure", "noslip", "noslip", "periodic", "periodic"), u_bc=uw, solid=solid)
+    rng = np.random.default_rng(nsteps)
+    rho = 1 + rng.uniform(-0.01, 0.01, shape[::-1])
+    u = rng.uniform(-0.03, 0.03, (3,) + shape[::-1])
+    g.init_equilibrium(rho, u)
+    o.init_equilibrium(rho, u)
+    g.step(nsteps)
+    o.step(nsteps)
+    assert g.time == nsteps
+    err = max_rel(g.get_pdfs(), o.get_pdfs(), solid)
+    assert err <= 1e-6, err
+    # gather agrees with the full read
+    cells = np.flatnonzero(solid.reshape(-1) == 0)[::7]
+    gat = g.gather(cells).cpu().numpy()
+    full = g.get_pdfs().cpu().numpy().reshape(q, -1)[:, cells].T
+    assert np.array_equal(gat, full)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_every_boundary_kind_on_every_axis(q):
+    """No-slip, velocity and pressure faces on all three axes with solids and
+    a force, 300 steps."""
+    shape = (20, 14, 10)
+    solid = np.zeros(shape[::-1], np.uint8)
+    solid[4:6, 6:9, 8:12] = 1
+    solid[0, 0, :] = 1  # solid cells touching faces and corners
+    uw = np.zeros((6, 3))
+    uw[0] = (0.02, 0.0, 0.001)
+    uw[3] = (0.01, -0.002, 0.0)
+    uw[4] = (0.0, 0.005, 0.01)
+    rb = np.array([1.0, 1.002, 1.0, 1.0, 1.0, 0.999])
+    bc = ("velocity", "pressure", "noslip", "velocity", "velocity", "pressure")
+    g, o = pair(shape, q=q, tau=0.8, force=(1e-5, 2e-6, -3e-6), bc=bc, u_bc=uw, rho_bc=rb, solid=solid)
+    rho, u = inputs.uniform_flow(*shape, (0.01, 0.0, 0.0))
+    g.init_equilibrium(rho, u)
+    o.init_equilibrium(rho, u)
+    g.step(300)
+    o.step(300)
+    err = max_rel(g.get_pdfs(), o.get_pdfs(), solid)
+    print("all-bc err", err)
+    assert err <= TOL32
+
+
+def test_channel_1000_steps():
+    """Channel shape (walls on y, periodic x and z, force in x, parabola plus
+    5% noise), a 64x32x32 copy of the 256x128x128 channel, 1000 steps."""
+    nx, ny, nz = 64, 32, 32
+    F = 8 * (1 / 300) * 0.05 / ny ** 2
+    g, o = pair((nx, ny, nz), tau=0.51, force=(F, 0, 0), bc=("periodic", "periodic", "noslip", "noslip",
+                                                             "periodic", "periodic"))
+    rho, u = inputs.channel(nx, ny, nz, 0.05, 0.05, seed=1234)
+    g.init_equilibrium(rho, u)
+    o.init_equilibrium(rho, u)
+    g.step(1000)
+    o.step(1000)
+    err = max_rel(g.get_pdfs(), o.get_pdfs())
+    print("channel copy err", err)
+    assert err <= TOL32
+    mg, _ = g.totals()
+    mo, _ = o.totals()
+    assert abs(mg - nx * ny * nz) / (nx * ny * nz) < 1e-6  # FP32 mass drift after 1000 steps
+    assert abs(mg - mo) / mo < 1e-7
+
+
+def test_obstacle_d3q27_200_steps():
+    """D3Q27 obstacle flow: velocity inflow 0.04 at -x, pressure outflow at
+    +x, periodic y/z, random spheres (10% solid, radii 4-10), 96x64x64, 200 steps."""
+    shape = (96, 64, 64)
+    solid, _ = inputs.spheres(*shape, fill=0.10, rmin=4, rmax=10, x_margin=8, seed=2024)
+    uw = np.zeros((6, 3))
+    uw[0] = (0.04, 0, 0)
+    g, o = pair(shape, q=27, tau=0.56, bc=("velocity", "pressure", "periodic", "periodic", "periodic",
+                                            "periodic"), u_bc=uw, solid=solid)
+    rho, u = inputs.uniform_flow(*shape, (0.04, 0, 0))
+    u[:, solid == 1] = 0.0
+    g.init_equilibrium(rho, u)
+    o.init_equilibrium(rho, u)
+    g.step(200)
+    o.step(200)
+    err = max_rel(g.get_pdfs(), o.get_pdfs(), solid)
+    print("obstacle err", err)
+    assert err <= TOL32
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_smagorinsky_closure(q):
+    nx, ny, nz = 32, 16, 16
+    g, o = pair((nx, ny, nz), q=q, tau=0.505, force=(2e-6, 0, 0), closure="smagorinsky", cs=0.1,
+                bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"))
+    rho, u = inputs.channel(nx, ny, nz, 0.08, 0.2, seed=3)
+    g.init_equilibrium(rho, u)
+    o.init_equilibrium(rho, u)
+    g.step(500)
+    o.step(500)
+    err = max_rel(g.get_pdfs(), o.get_pdfs())
+    print("smagorinsky err", err)
+    assert err <= TOL32
+
+
+# ---------------------------------------------------------------------------
+# state readers and robustness
+# ---------------------------------------------------------------------------
+def test_moments_and_set_pdfs_roundtrip():
+    shape = (24, 10, 6)
+    g, o = pair(shape, force=(1e-4, 0, 0), bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"))
+    c, w, _ = oracle.velocity_set(19)
+    W = w[:, None, None, None]
+    f = W * (1.0 + inputs.perturbation((19,) + shape[::-1], 0.05, seed=1))
+    g.set_pdfs(f)
+    o.set_pdfs(f)
+    back = g.get_pdfs().cpu().numpy()
+    expect = (f - W).astype(np.float32).astype(np.float64) + W
+    assert np.array_equal(back, expect)
+    r, uu = g.moments()
+    ro, uo = o.moments()
+    assert np.abs(r.cpu().numpy() - ro).max() < 1e-6
+    assert np.abs(uu.cpu().numpy() - uo).max() < 1e-6
+    mg, pg = g.totals()
+    mo, po = o.totals()
+    # the GPU holds each deviation rounded to FP32 (error <= 2^-24 |f - w|)
+    bound = 2.0 ** -24 * np.abs(f - W).sum()
+    assert abs(mg - mo) <= bound and np.abs(pg - po).max() <= bound
+
+
+@pytest.mark.parametrize("storage,tdtype", [("f16", torch.float16), ("bf16", torch.bfloat16)])
+def test_low_precision_storage_rounding(storage, tdtype):
+    """Stored deviations equal torch's round-to-nearest-even conversion of the
+    FP32 deviation, subnormals included."""
+    shape = (16, 8, 4)
+    g = _lbm().Lattice(shape, storage=storage)
+    c, w, _ = oracle.velocity_set(19)
+    rng = np.random.default_rng(2)
+    dev = rng.normal(0, 1e-3, (19,) + shape[::-1])
+    dev.reshape(19, -1)[:, :64] = rng.normal(0, 1e-7, (19, 64))  # FP16 subnormal range
+    f = dev + w[:, None, None, None]
+    g.set_pdfs(f)
+    got = g.get_pdfs().cpu().numpy() - w[:, None, None, None]
+    d32 = torch.from_numpy((f - w[:, None, None, None]).astype(np.float32))
+    expect = d32.to(tdtype).to(torch.float64).numpy()
+    assert np.allclose(got, expect, rtol=0, atol=1e-17)
+
+
+def test_run_twice_bit_identical_and_checkpoint_resume():
+    shape = (32, 16, 8)
+    kw = dict(tau=0.55, force=(1e-5, 0, 0), bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"))
+    lbm = _lbm()
+    rho, u = inputs.channel(*shape, 0.05, 0.05, seed=7)
+    a = lbm.Lattice(shape, **kw)
+    a.init_equilibrium(rho, u)
+    a.step(101)
+    buf, t = a.save_state()
+    a.step(101)
+    fa = a.get_pdfs()
+    b = lbm.Lattice(shape, **kw)
+    b.init_equilibrium(rho, u)
+    b.step(202)
+    assert torch.equal(fa, b.get_pdfs())
+    c = lbm.Lattice(shape, **kw)
+    c.load_state(buf, t)
+    assert c.time == 101
+    c.step(101)
+    assert torch.equal(fa, c.get_pdfs())
+    ma, pa = a.totals()
+    mb, pb = b.totals()
+    assert ma == mb and np.array_equal(pa, pb)
+
+
+def test_nonfinite_detected_and_errors_reported():
+    lbm = _lbm()
+    shape = (16, 8, 8)
+    g = lbm.Lattice(shape)
+    c, w, _ = oracle.velocity_set(19)
+    f = np.broadcast_to(w[:, None, None, None], (19,) + shape[::-1]).copy()
+    f[3, 2, 5, 7] = np.nan
+    g.set_pdfs(f)
+    rc, _, _ = g.totals(check=False)
+    assert rc == lbm.LBM_ENONFINITE
+    with pytest.raises(lbm.LBMError) as e:
+        g.step(-1)
+    assert e.value.code == lbm.LBM_EINVAL
+    m = lbm.Lattice(shape, closure="mlp")
+    with pytest.raises(lbm.LBMError) as e:
+        m.step(1)
+    assert e.value.code == lbm.LBM_ESTATE
+
+
+def test_stream_copy_probe():
+    lbm = _lbm()
+    src = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    lbm.stream_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
