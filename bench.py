@@ -87,7 +87,7 @@ def time_lattice(cfg, steps, warmup, diag_every=1000):
     done = 0
     diag = []
     while done < steps:
-        k = min(diag_every, steps - done)
+        k = min(diag_every, steps - done) if diag_every > 0 else steps - done
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -167,6 +167,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="headline workload only")
     ap.add_argument("--form-steps", type=int, default=300)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy this many MiB once with the library's copy kernel (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the multi-GPU halo "
@@ -178,6 +180,16 @@ def main():
         sys.exit(1)
     from paper_2305_09910_amd import lbm
     lbm.lib()
+
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        lbm.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
+        torch.cuda.empty_cache()
 
     head = channel_cfg(256, 128, 128)
     log(f"[bench] headline {head['name']} f32, warmup {args.warmup}, steps {args.steps}")

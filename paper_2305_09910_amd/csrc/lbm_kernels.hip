@@ -38,7 +38,40 @@
 #include "mlp_wave.h"
 #include "stencil.h"
 
+// Tuning knobs (measured choices are the defaults): streaming hints on the
+// population loads/stores and the minimum number of waves per SIMD the
+// register allocation must allow for the stream-collide kernel.
+#ifndef LBM_NT_LOAD
+#define LBM_NT_LOAD 0
+#endif
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 0
+#endif
+#ifndef LBM_MIN_WAVES
+#define LBM_MIN_WAVES 1
+#endif
+
 namespace lbm {
+
+template <class T>
+__device__ inline T ld_pop(const T *p)
+{
+#if LBM_NT_LOAD
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <class T>
+__device__ inline void st_pop(T *p, T v)
+{
+#if LBM_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
 
 // ---------------------------------------------------------------------------
 // storage formats
@@ -49,16 +82,16 @@ struct Store;
 template <>
 struct Store<ST_F32> {
     using T = float;
-    __device__ static float ld(const T *p) { return *p; }
-    __device__ static void st(T *p, float v) { *p = v; }
+    __device__ static float ld(const T *p) { return ld_pop(p); }
+    __device__ static void st(T *p, float v) { st_pop(p, v); }
     __device__ static T cvt(float v) { return v; }
 };
 
 template <>
 struct Store<ST_F16> {
     using T = _Float16;
-    __device__ static float ld(const T *p) { return (float)*p; }
-    __device__ static void st(T *p, float v) { *p = (_Float16)v; }
+    __device__ static float ld(const T *p) { return (float)ld_pop(p); }
+    __device__ static void st(T *p, float v) { st_pop(p, (_Float16)v); }
     __device__ static T cvt(float v) { return (_Float16)v; }
 };
 
@@ -74,8 +107,8 @@ __device__ inline uint16_t f32_to_bf16_rne(float v)
 template <>
 struct Store<ST_BF16> {
     using T = uint16_t;
-    __device__ static float ld(const T *p) { return __uint_as_float((uint32_t)*p << 16); }
-    __device__ static void st(T *p, float v) { *p = f32_to_bf16_rne(v); }
+    __device__ static float ld(const T *p) { return __uint_as_float((uint32_t)ld_pop(p) << 16); }
+    __device__ static void st(T *p, float v) { st_pop(p, f32_to_bf16_rne(v)); }
     __device__ static T cvt(float v) { return f32_to_bf16_rne(v); }
 };
 
@@ -303,7 +336,7 @@ __device__ inline float wall_value(const LatticeArgs &a, int face, int i, float 
 // the fused stream-collide kernel
 // ---------------------------------------------------------------------------
 template <int Q, int ST, int CL, bool MASK>
-__global__ void __launch_bounds__(256) k_stream_collide(LatticeArgs a, int odd)
+__global__ void __launch_bounds__(256, LBM_MIN_WAVES) k_stream_collide(LatticeArgs a, int odd)
 {
     using S = Store<ST>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
