@@ -56,10 +56,50 @@ def obstacle_cfg(n=384):
                 storage="f32", closure="none", solid=solid, u_bc=uw)
 
 
+def demo_closure_weights(seed=9):
+    """Seeded network weights for timing the fused closure (the kernel's cost
+    does not depend on their values); the trusted input range is unbounded."""
+    rng = np.random.default_rng(seed)
+    p = np.concatenate([rng.normal(0, 0.3, 192), rng.normal(0, 0.1, 32), rng.normal(0, 0.15, 1024),
+                        rng.normal(0, 0.1, 32), rng.normal(0, 0.1, 32), [-5.0]])
+    norm = np.concatenate([np.zeros(6), [1e-3, 1e-3, 1e-3, 1e-2, 1e-2, 1.0], np.full(6, -1e30), np.full(6, 1e30)])
+    return np.concatenate([p, norm]).astype(np.float32)
+
+
+KERNEL_SOURCES = ["paper_2305_09910_amd/csrc/lbm_kernels.hip", "paper_2305_09910_amd/csrc/stencil.h",
+                  "paper_2305_09910_amd/csrc/internal.h", "paper_2305_09910_amd/csrc/mlp_wave.h"]
+PROFILE = "profiles/stream_collide_channel_256x128x128.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    import re
+    path = os.path.join(ROOT, PROFILE)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel source sha256\[:16\]: `([0-9a-f]+)`", txt)
+    t = re.search(r"HBM traffic per launch \(scaled\): ([0-9.]+) MB", txt)
+    if not m or not t or m.group(1) != kernel_source_hash():
+        return None
+    return float(t.group(1)) * 1e6
+
+
 def make_lattice(cfg):
     from paper_2305_09910_amd import inputs, lbm
     lat = lbm.Lattice(cfg["shape"], q=cfg["q"], tau=cfg["tau"], force=cfg["force"], bc=cfg["bc"],
                       u_bc=cfg["u_bc"], solid=cfg["solid"], storage=cfg["storage"], closure=cfg["closure"])
+    if cfg["closure"] == "mlp":
+        lat.set_closure_weights(demo_closure_weights())
     nx, ny, nz = cfg["shape"]
     if cfg["name"].startswith("channel"):
         rho, u = inputs.channel(nx, ny, nz, 0.05, 0.05, seed=1234)
@@ -209,6 +249,8 @@ def main():
             ("channel_512x256x256_bf16", channel_cfg(512, 256, 256, "bf16")),
             ("obstacles_384^3_d3q27_f32", obstacle_cfg()),
             ("channel_256x128x128_smagorinsky", channel_cfg(256, 128, 128, "f32", "smagorinsky")),
+            ("channel_256x128x128_mlp_closure", channel_cfg(256, 128, 128, "f32", "mlp")),
+            ("channel_512x256x256_mlp_closure", channel_cfg(512, 256, 256, "f32", "mlp")),
         ]
         for key, cfg in plan:
             log(f"[bench] form {key}, {fs} steps")
@@ -225,6 +267,7 @@ def main():
         cpu = cpu_baseline(head)
         log(f"[bench]   {cpu}")
 
+    traffic = profiled_traffic()
     out = {
         "metric": "MLUPS and % HBM roofline, FP32 vs FP16-storage vs learned-closure",
         "value": round(r["mlups"], 1),
@@ -242,7 +285,10 @@ def main():
                    "cells": r["cells"], "stencil": "D3Q19", "storage": "f32", "tau": head["tau"],
                    "force_x": head["force"][0], "diagnostics_every": 1000},
         "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(r["roofline_frac"], 4), "traffic": None,
+                     "frac": round(r["roofline_frac"], 4),
+                     "traffic": (round(traffic / 1e6, 1) if traffic else None),
+                     "traffic_unit": "MB per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_mb_per_launch": round(r["bytes_per_cell"] * r["cells"] / 1e6, 1),
                      "kernel": "k_stream_collide<19,f32,none> (one launch per step)",
                      "bytes_per_cell": r["bytes_per_cell"], "kernel_us": round(r["kernel_ms"] * 1e3, 2)},
         "cpu_baseline": cpu,

@@ -11,7 +11,7 @@
  *     and an optional per-cell solid mask,
  *   - one population set kept in place in HBM (AA access pattern, the family
  *     of in-place schemes the paper's Esoteric Twist belongs to, Section 5.2),
- *     structure-of-arrays layout [q][z][y][x],
+ *     structure of arrays within each row of cells: [z][y][q][x],
  *   - optional LES closures (Smagorinsky, or a small learned MLP) that set a
  *     per-cell relaxation time.
  *

@@ -187,3 +187,45 @@ def study(cfg: ClosureConfig, log=print):
     res = {"a_priori_train": a_priori(P, x, t), "a_priori_heldout": a_priori(P, xh, th), "loss_history": hist}
     res["a_posteriori"] = a_posteriori(cfg, P, filt, fine, log)
     return res, P
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="learned LES closure study (fine run -> filter -> train -> compare)")
+    ap.add_argument("--coarse", type=int, nargs=3, default=[256, 128, 128])
+    ap.add_argument("--tau-c", type=float, default=0.503)
+    ap.add_argument("--noise", type=float, default=0.3)
+    ap.add_argument("--spinup", type=int, default=1000)
+    ap.add_argument("--snapshots", type=int, default=4)
+    ap.add_argument("--every", type=int, default=500)
+    ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--eval-coarse-steps", type=int, default=500)
+    ap.add_argument("--out", default=None, help="write the JSON result here")
+    a = ap.parse_args(argv)
+    cfg = ClosureConfig(coarse=tuple(a.coarse), tau_c=a.tau_c, noise=a.noise, spinup=a.spinup,
+                        snapshots=a.snapshots, every=a.every, train_steps=a.train_steps, batch=a.batch, lr=a.lr,
+                        eval_coarse_steps=a.eval_coarse_steps)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    log(f"[closure] fine {cfg.fine}, coarse {cfg.coarse}, tau_c {cfg.tau_c}, F_c {cfg.force_c:.3e}")
+    res, P = study(cfg, log)
+    res["config"] = {k: getattr(cfg, k) for k in ("coarse", "factor", "tau_c", "u_c", "re_tau", "noise", "seed", "cs",
+                                                   "spinup", "snapshots", "every", "train_steps", "batch", "lr",
+                                                   "eval_coarse_steps")}
+    res["config"]["fine"] = cfg.fine
+    line = json.dumps(res)
+    print(line, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(line + "\n")
+        np.save(a.out.replace(".json", "_weights.npy"), P.cpu().numpy())
+
+
+if __name__ == "__main__":
+    main()

@@ -22,11 +22,10 @@ constexpr int MLP_NNORM = 24;
 
 // Everything a lattice kernel needs, passed by value.
 struct LatticeArgs {
-    void *pdf;               // [q][n] storage elements (deviations f_i - w_i)
+    void *pdf;               // [z][y][q][x] storage elements (deviations f_i - w_i)
     const uint32_t *mask;    // [n] or nullptr
     int nx, ny, nz;
     uint32_t n;              // cells
-    uint64_t plane;          // elements per direction plane (== n)
     int per[3];              // axis periodic?
     int bc[6];               // face kinds
     int any_vp;              // any velocity / pressure face

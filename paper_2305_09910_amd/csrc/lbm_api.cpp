@@ -4,7 +4,7 @@
 // caller's stream.  The library allocates no device memory: everything lives
 // in the caller's workspace.  Layout of the workspace (each part 256-byte
 // aligned):
-//   populations  q * n storage elements, [q][z][y][x]
+//   populations  q * n storage elements, [z][y][q][x] (rows of q direction segments)
 //   mask         n uint32 words (only with use_flags)
 //   totals       partial sums (1024 blocks x 5 doubles) and the final 5
 //   closure      MLP parameters (1313 + 24 FP32) and a fallback counter
@@ -174,7 +174,6 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     a.ny = d->ny;
     a.nz = d->nz;
     a.n = (uint32_t)((uint64_t)d->nx * d->ny * d->nz);
-    a.plane = a.n;
     for (int k = 0; k < 3; ++k) a.per[k] = d->bc[2 * k] == LBM_BC_PERIODIC;
     a.any_vp = 0;
     for (int f = 0; f < 6; ++f) {

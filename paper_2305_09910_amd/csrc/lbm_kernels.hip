@@ -1,7 +1,9 @@
 // lbm_kernels.hip -- fused in-place stream-collide kernels for gfx950.
 //
-// One population set lives in HBM as deviations d_i = f_i - w_i, structure
-// of arrays [q][z][y][x].  Streaming (the paper's Eq. (2)) and collision
+// One population set lives in HBM as deviations d_i = f_i - w_i, in rows of
+// q direction segments [z][y][q][x]: structure of arrays within each row,
+// so every wavefront access to one direction is contiguous, with the q
+// segments of a row kept together in one block.  Streaming (the paper's Eq. (2)) and collision
 // (Eq. (1), read as TRT with Guo forcing) are fused into one kernel per time
 // step with the AA access pattern, an in-place scheme of the same family as
 // the Esoteric Twist the paper's LAGOON runs use (Section 5.2):
@@ -38,40 +40,50 @@
 #include "mlp_wave.h"
 #include "stencil.h"
 
-// Tuning knobs (measured choices are the defaults): streaming hints on the
-// population loads/stores and the minimum number of waves per SIMD the
-// register allocation must allow for the stream-collide kernel.
-#ifndef LBM_NT_LOAD
-#define LBM_NT_LOAD 0
-#endif
-#ifndef LBM_NT_STORE
-#define LBM_NT_STORE 0
-#endif
+// Tuning knobs: the minimum number of waves per SIMD the register
+// allocation must allow for the stream-collide kernel, the workgroup size,
+// and the streaming (nontemporal) hints of the plain path (1: measured
+// policy, 0: none, 2: everywhere).
 #ifndef LBM_MIN_WAVES
 #define LBM_MIN_WAVES 1
+#endif
+#ifndef LBM_BLOCK
+#define LBM_BLOCK 256
+#endif
+#ifndef LBM_NT_POLICY
+#define LBM_NT_POLICY 1
 #endif
 
 namespace lbm {
 
-template <class T>
+// Streaming hints.  A population line that only this wavefront touches is
+// loaded and stored with the nontemporal hint (no reuse; it should not
+// displace other lines).  Lines read with a +-1 shift along x are shared
+// with the neighbouring wavefront in the same workgroup, so those keep the
+// normal policy and meet in L2.
+template <bool NT, class T>
 __device__ inline T ld_pop(const T *p)
 {
-#if LBM_NT_LOAD
-    return __builtin_nontemporal_load(p);
-#else
+    if constexpr (NT) return __builtin_nontemporal_load(p);
     return *p;
-#endif
 }
 
-template <class T>
+template <bool NT, class T>
 __device__ inline void st_pop(T *p, T v)
 {
-#if LBM_NT_STORE
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
+
+// hint for a population access along direction i on the even (local) or
+// odd (shifted) step of the plain path
+template <int I>
+struct Hint {
+    static constexpr bool even = LBM_NT_POLICY != 0;
+    static constexpr bool odd = LBM_NT_POLICY == 2 || (LBM_NT_POLICY == 1 && cdir(I, 0) == 0);
+};
 
 // ---------------------------------------------------------------------------
 // storage formats
@@ -82,16 +94,20 @@ struct Store;
 template <>
 struct Store<ST_F32> {
     using T = float;
-    __device__ static float ld(const T *p) { return ld_pop(p); }
-    __device__ static void st(T *p, float v) { st_pop(p, v); }
+    template <bool NT = false>
+    __device__ static float ld(const T *p) { return ld_pop<NT>(p); }
+    template <bool NT = false>
+    __device__ static void st(T *p, float v) { st_pop<NT>(p, v); }
     __device__ static T cvt(float v) { return v; }
 };
 
 template <>
 struct Store<ST_F16> {
     using T = _Float16;
-    __device__ static float ld(const T *p) { return (float)ld_pop(p); }
-    __device__ static void st(T *p, float v) { st_pop(p, (_Float16)v); }
+    template <bool NT = false>
+    __device__ static float ld(const T *p) { return (float)ld_pop<NT>(p); }
+    template <bool NT = false>
+    __device__ static void st(T *p, float v) { st_pop<NT>(p, (_Float16)v); }
     __device__ static T cvt(float v) { return (_Float16)v; }
 };
 
@@ -107,8 +123,10 @@ __device__ inline uint16_t f32_to_bf16_rne(float v)
 template <>
 struct Store<ST_BF16> {
     using T = uint16_t;
-    __device__ static float ld(const T *p) { return __uint_as_float((uint32_t)ld_pop(p) << 16); }
-    __device__ static void st(T *p, float v) { st_pop(p, f32_to_bf16_rne(v)); }
+    template <bool NT = false>
+    __device__ static float ld(const T *p) { return __uint_as_float((uint32_t)ld_pop<NT>(p) << 16); }
+    template <bool NT = false>
+    __device__ static void st(T *p, float v) { st_pop<NT>(p, f32_to_bf16_rne(v)); }
     __device__ static T cvt(float v) { return f32_to_bf16_rne(v); }
 };
 
@@ -117,7 +135,8 @@ struct Store<ST_BF16> {
 // ---------------------------------------------------------------------------
 struct Geom {
     int x, y, z;
-    uint32_t c;
+    uint32_t c;    // cell index (z ny + y) nx + x of fields and the mask
+    uint32_t row;  // row index z ny + y of the population store
     int xm, xp, ym, yp, zm, zp;    // wrapped neighbour coordinates
     bool cxl, cxh, cyl, cyh, czl, czh;  // link through that face is cut by a non-periodic face
 };
@@ -128,7 +147,8 @@ __device__ inline Geom make_geom(const LatticeArgs &a, int x, int y, int z)
     g.x = x;
     g.y = y;
     g.z = z;
-    g.c = ((uint32_t)z * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx + (uint32_t)x;
+    g.row = (uint32_t)z * (uint32_t)a.ny + (uint32_t)y;
+    g.c = g.row * (uint32_t)a.nx + (uint32_t)x;
     g.xm = x == 0 ? a.nx - 1 : x - 1;
     g.xp = x == a.nx - 1 ? 0 : x + 1;
     g.ym = y == 0 ? a.ny - 1 : y - 1;
@@ -151,6 +171,32 @@ __device__ inline uint32_t nbr(const LatticeArgs &a, const Geom &g, int dx, int 
     const int yy = dy < 0 ? g.ym : (dy > 0 ? g.yp : g.y);
     const int zz = dz < 0 ? g.zm : (dz > 0 ? g.zp : g.z);
     return ((uint32_t)zz * (uint32_t)a.ny + (uint32_t)yy) * (uint32_t)a.nx + (uint32_t)xx;
+}
+
+// Population store: rows of q direction segments, [z][y][i][x].  Each
+// segment holds the nx populations of one direction of one row, so a
+// wavefront's accesses for one direction are contiguous, and the q segments
+// of a row sit together (one block of q nx elements per row).
+template <int Q>
+__device__ inline uint64_t pidx(const LatticeArgs &a, int i, uint32_t row, int x)
+{
+    return ((uint64_t)row * Q + (uint64_t)i) * (uint32_t)a.nx + (uint32_t)x;
+}
+
+// row and x of the neighbour at offset (dx, dy, dz), periodic wrap
+__device__ inline uint32_t nbr_row(const LatticeArgs &a, const Geom &g, int dy, int dz)
+{
+    const int yy = dy < 0 ? g.ym : (dy > 0 ? g.yp : g.y);
+    const int zz = dz < 0 ? g.zm : (dz > 0 ? g.zp : g.z);
+    return (uint32_t)zz * (uint32_t)a.ny + (uint32_t)yy;
+}
+
+__device__ inline int nbr_x(const Geom &g, int dx) { return dx < 0 ? g.xm : (dx > 0 ? g.xp : g.x); }
+
+template <int Q>
+__device__ inline uint64_t pidx_nbr(const LatticeArgs &a, const Geom &g, int i, int dx, int dy, int dz)
+{
+    return pidx<Q>(a, i, nbr_row(a, g, dy, dz), nbr_x(g, dx));
 }
 
 // does the link from this cell along (dx, dy, dz) leave through a non-periodic face?
@@ -189,20 +235,71 @@ __device__ inline void load_canonical(const LatticeArgs &a, const Geom &g, uint3
 {
     using S = Store<ST>;
     const typename S::T *A = (const typename S::T *)a.pdf;
-    const uint64_t N = a.plane;
     if (!odd) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = S::ld(A + (uint64_t)i * N + g.c);
+        for (int i = 0; i < Q; ++i) d[i] = S::ld(A + pidx<Q>(a, i, g.row, g.x));
     } else {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
             // source x - c_i; blocked when that link is cut (mask bit of opposite(i))
             const bool cut = face_cut(g, -dx, -dy, -dz) || ((m >> opp(i)) & 1u);
-            const uint64_t own = (uint64_t)i * N + g.c;
-            const uint64_t src = (uint64_t)opp(i) * N + nbr(a, g, -dx, -dy, -dz);
+            const uint64_t own = pidx<Q>(a, i, g.row, g.x);
+            const uint64_t src = pidx_nbr<Q>(a, g, opp(i), -dx, -dy, -dz);
             d[i] = S::ld(A + (cut ? own : src));
         }
+    }
+}
+
+// Compile-time loop over the directions (so each access can take its own
+// streaming hint).
+template <int I, int Q, class F>
+__device__ inline void for_dirs(F &&f)
+{
+    if constexpr (I < Q) {
+        f(std::integral_constant<int, I>{});
+        for_dirs<I + 1, Q>(f);
+    }
+}
+
+// Read of a cell none of whose links is cut (no non-periodic face next to
+// it, no solid neighbour): no wall logic; on the even step all q segments
+// of the cell's own row block.
+template <int Q, int ST>
+__device__ inline void load_plain(const LatticeArgs &a, const Geom &g, int odd, float (&d)[Q])
+{
+    using S = Store<ST>;
+    const typename S::T *A = (const typename S::T *)a.pdf;
+    if (!odd) {
+        const typename S::T *R = A + pidx<Q>(a, 0, g.row, g.x);
+        for_dirs<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            d[i] = S::template ld<Hint<i>::even>(R + (uint64_t)i * (uint32_t)a.nx);
+        });
+    } else {
+        for_dirs<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            d[i] = S::template ld<Hint<i>::odd>(A + pidx_nbr<Q>(a, g, opp(i), -cdir(i, 0), -cdir(i, 1), -cdir(i, 2)));
+        });
+    }
+}
+
+template <int Q, int ST>
+__device__ inline void store_plain(const LatticeArgs &a, const Geom &g, int odd, const float (&d)[Q])
+{
+    using S = Store<ST>;
+    typename S::T *A = (typename S::T *)a.pdf;
+    if (!odd) {
+        typename S::T *R = A + pidx<Q>(a, 0, g.row, g.x);
+        for_dirs<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            S::template st<Hint<i>::even>(R + (uint64_t)opp(i) * (uint32_t)a.nx, d[i]);
+        });
+    } else {
+        for_dirs<0, Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            S::template st<Hint<i>::odd>(A + pidx_nbr<Q>(a, g, i, cdir(i, 0), cdir(i, 1), cdir(i, 2)), d[i]);
+        });
     }
 }
 
@@ -336,7 +433,7 @@ __device__ inline float wall_value(const LatticeArgs &a, int face, int i, float 
 // the fused stream-collide kernel
 // ---------------------------------------------------------------------------
 template <int Q, int ST, int CL, bool MASK>
-__global__ void __launch_bounds__(256, LBM_MIN_WAVES) k_stream_collide(LatticeArgs a, int odd)
+__global__ void __launch_bounds__(LBM_BLOCK, LBM_MIN_WAVES) k_stream_collide(LatticeArgs a, int odd)
 {
     using S = Store<ST>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -358,14 +455,14 @@ __global__ void __launch_bounds__(256, LBM_MIN_WAVES) k_stream_collide(LatticeAr
             active = false;
         }
     }
+    // no link of this cell is cut: the common case, without wall logic
+    const bool plain = !(g.cxl || g.cxh || g.cyl || g.cyh || g.czl || g.czh) && (m & ~SELF_SOLID) == 0u;
     float d[Q];
-    if constexpr (CL == CL_MLP) {
-        if (active) {
-            load_canonical<Q, ST>(a, g, m, odd, d);
-        } else {
+    if (CL == CL_MLP && !active) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) d[i] = 0.f;
-        }
+        for (int i = 0; i < Q; ++i) d[i] = 0.f;
+    } else if (plain) {
+        load_plain<Q, ST>(a, g, odd, d);
     } else {
         load_canonical<Q, ST>(a, g, m, odd, d);
     }
@@ -405,8 +502,9 @@ __global__ void __launch_bounds__(256, LBM_MIN_WAVES) k_stream_collide(LatticeAr
     }
 
     typename S::T *A = (typename S::T *)a.pdf;
-    const uint64_t N = a.plane;
-    if (!odd) {
+    if (plain) {
+        store_plain<Q, ST>(a, g, odd, d);
+    } else if (!odd) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             float v = d[i];
@@ -414,7 +512,7 @@ __global__ void __launch_bounds__(256, LBM_MIN_WAVES) k_stream_collide(LatticeAr
                 const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
                 if (face_cut(g, dx, dy, dz)) v = wall_value<Q>(a, deciding_face(a, g, dx, dy, dz), i, v, M);
             }
-            S::st(A + (uint64_t)opp(i) * N + g.c, v);
+            S::st(A + pidx<Q>(a, opp(i), g.row, g.x), v);
         }
     } else {
 #pragma unroll
@@ -424,8 +522,8 @@ __global__ void __launch_bounds__(256, LBM_MIN_WAVES) k_stream_collide(LatticeAr
             const bool cut = fcut || ((m >> i) & 1u);
             float v = d[i];
             if (a.any_vp && fcut) v = wall_value<Q>(a, deciding_face(a, g, dx, dy, dz), i, v, M);
-            const uint64_t own = (uint64_t)opp(i) * N + g.c;
-            const uint64_t dst = (uint64_t)i * N + nbr(a, g, dx, dy, dz);
+            const uint64_t own = pidx<Q>(a, opp(i), g.row, g.x);
+            const uint64_t dst = pidx_nbr<Q>(a, g, i, dx, dy, dz);
             S::st(A + (cut ? own : dst), v);
         }
     }
@@ -435,7 +533,7 @@ __global__ void __launch_bounds__(256, LBM_MIN_WAVES) k_stream_collide(LatticeAr
 // set-up and state kernels
 // ---------------------------------------------------------------------------
 template <int Q>
-__global__ void __launch_bounds__(256) k_build_mask(LatticeArgs a, const uint8_t *flags, uint32_t *mask)
+__global__ void __launch_bounds__(LBM_BLOCK) k_build_mask(LatticeArgs a, const uint8_t *flags, uint32_t *mask)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -452,7 +550,7 @@ __global__ void __launch_bounds__(256) k_build_mask(LatticeArgs a, const uint8_t
 }
 
 template <int Q, int ST>
-__global__ void __launch_bounds__(256) k_init_eq(LatticeArgs a, const double *rho, const double *u)
+__global__ void __launch_bounds__(LBM_BLOCK) k_init_eq(LatticeArgs a, const double *rho, const double *u)
 {
     using S = Store<ST>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -461,19 +559,19 @@ __global__ void __launch_bounds__(256) k_init_eq(LatticeArgs a, const double *rh
     if (x >= a.nx || y >= a.ny) return;
     const Geom g = make_geom(a, x, y, z);
     const bool solid = a.mask && (a.mask[g.c] & SELF_SOLID);
-    const double r = rho[g.c], ux = u[g.c], uy = u[a.plane + g.c], uz = u[2 * a.plane + g.c];
+    const double r = rho[g.c], ux = u[g.c], uy = u[(uint64_t)a.n + g.c], uz = u[2 * (uint64_t)a.n + g.c];
     const double usq = ux * ux + uy * uy + uz * uz;
     typename S::T *A = (typename S::T *)a.pdf;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const double cu = cdir(i, 0) * ux + cdir(i, 1) * uy + cdir(i, 2) * uz;
         const double dev = wgt<Q>(i) * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
-        A[(uint64_t)i * a.plane + g.c] = S::cvt(solid ? 0.f : (float)dev);
+        A[pidx<Q>(a, i, g.row, g.x)] = S::cvt(solid ? 0.f : (float)dev);
     }
 }
 
 template <int Q, int ST>
-__global__ void __launch_bounds__(256) k_set_pdfs(LatticeArgs a, const double *f)
+__global__ void __launch_bounds__(LBM_BLOCK) k_set_pdfs(LatticeArgs a, const double *f)
 {
     using S = Store<ST>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -484,13 +582,12 @@ __global__ void __launch_bounds__(256) k_set_pdfs(LatticeArgs a, const double *f
     typename S::T *A = (typename S::T *)a.pdf;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const uint64_t k = (uint64_t)i * a.plane + g.c;
-        A[k] = S::cvt((float)(f[k] - wgt<Q>(i)));
+        A[pidx<Q>(a, i, g.row, g.x)] = S::cvt((float)(f[(uint64_t)i * a.n + g.c] - wgt<Q>(i)));
     }
 }
 
 template <int Q, int ST>
-__global__ void __launch_bounds__(256) k_get_pdfs(LatticeArgs a, int odd, double *f)
+__global__ void __launch_bounds__(LBM_BLOCK) k_get_pdfs(LatticeArgs a, int odd, double *f)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -506,7 +603,7 @@ __global__ void __launch_bounds__(256) k_get_pdfs(LatticeArgs a, int odd, double
         load_canonical<Q, ST>(a, g, m, odd, d);
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[(uint64_t)i * a.plane + g.c] = wgt<Q>(i) + (double)d[i];
+    for (int i = 0; i < Q; ++i) f[(uint64_t)i * a.n + g.c] = wgt<Q>(i) + (double)d[i];
 }
 
 template <int Q, int ST>
@@ -536,7 +633,7 @@ __global__ void __launch_bounds__(256) k_gather(LatticeArgs a, int odd, const in
 }
 
 template <int Q, int ST>
-__global__ void __launch_bounds__(256) k_moments(LatticeArgs a, int odd, float *rho, float *u)
+__global__ void __launch_bounds__(LBM_BLOCK) k_moments(LatticeArgs a, int odd, float *rho, float *u)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -546,7 +643,7 @@ __global__ void __launch_bounds__(256) k_moments(LatticeArgs a, int odd, float *
     const uint32_t m = a.mask ? a.mask[g.c] : 0u;
     if (m & SELF_SOLID) {
         rho[g.c] = 1.f;
-        u[g.c] = u[a.plane + g.c] = u[2 * a.plane + g.c] = 0.f;
+        u[g.c] = u[(uint64_t)a.n + g.c] = u[2 * (uint64_t)a.n + g.c] = 0.f;
         return;
     }
     float d[Q];
@@ -555,8 +652,8 @@ __global__ void __launch_bounds__(256) k_moments(LatticeArgs a, int odd, float *
     const Macro M = moments<Q>(a, d, drho);
     rho[g.c] = M.rho;
     u[g.c] = M.ux;
-    u[a.plane + g.c] = M.uy;
-    u[2 * a.plane + g.c] = M.uz;
+    u[(uint64_t)a.n + g.c] = M.uy;
+    u[2 * (uint64_t)a.n + g.c] = M.uz;
 }
 
 // Deterministic FP64 totals: each block owns a fixed slice of cells and
@@ -625,10 +722,22 @@ __global__ void __launch_bounds__(64) k_totals_final(const double *partial, doub
     out[k] = v;
 }
 
+// Copy: every thread moves 4 float4, strided by the block so that each
+// wave touches four contiguous 1 KiB runs; grid = n / 1024 blocks.
 __global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ src, float4 *__restrict__ dst, size_t n)
 {
-    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
-        dst[k] = src[k];
+    const size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x;
+    float4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t i = base + 256 * k;
+        if (i < n) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t i = base + 256 * k;
+        if (i < n) dst[i] = v[k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -636,22 +745,14 @@ __global__ void __launch_bounds__(256) k_copy(const float4 *__restrict__ src, fl
 // ---------------------------------------------------------------------------
 Launch lattice_launch(const LatticeArgs &a)
 {
-    // Block = 256 threads: BX cells along x (a row segment) times BY rows.
+    // LBM_BLOCK threads: BX cells along x (a row segment) times BY rows.
     // Whole rows per block keep the +-1 shifted reads of the odd step inside
     // one workgroup (no cache line shared between blocks within a row).
-    int bx = 256;
-    if (a.nx % 256 != 0) {
-        bx = 32;
-        for (int c : {128, 64}) {
-            if (a.nx % c == 0) {
-                bx = c;
-                break;
-            }
-        }
-        if (a.nx < 32) bx = 32;
-        else if (a.nx % 32 != 0) bx = 64;
-    }
-    const int by = 256 / bx;
+    int bx = LBM_BLOCK;
+    while (bx > 32 && a.nx % bx != 0) bx >>= 1;
+    if (a.nx % bx != 0) bx = 64;  // ragged rows: masked tail
+    if (bx > a.nx) bx = a.nx <= 32 ? 32 : 64;
+    const int by = LBM_BLOCK / bx;
     Launch L;
     L.block = dim3(bx, by, 1);
     L.grid = dim3((a.nx + bx - 1) / bx, (a.ny + by - 1) / by, a.nz);
@@ -780,8 +881,9 @@ hipError_t launch_totals(const LatticeArgs &a, int q, int st, int odd, double *p
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
 {
     const size_t n = bytes / 16;
-    const size_t blocks = std::min<size_t>((n + 255) / 256, 256 * 8 * 16);
+    const size_t blocks = (n + 1023) / 1024;
     if (n == 0) return hipSuccess;
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
     k_copy<<<(unsigned)blocks, 256, 0, s>>>((const float4 *)src, (float4 *)dst, n);
     return hipGetLastError();
 }
