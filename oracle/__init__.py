@@ -76,6 +76,10 @@ def lib():
         L.orc_collide.argtypes = [ctypes.c_int, _D, ctypes.c_double, ctypes.c_double, _D, ctypes.c_int,
                                   ctypes.c_double, _D, _D]
         L.orc_noneq_flux.argtypes = [ctypes.c_int, _D, _D, _D]
+        L.orc_mrt_basis.argtypes = [ctypes.c_int, _D, _I]
+        L.orc_set_mrt.argtypes = [ctypes.c_void_p, _D]
+        L.orc_collide_mrt.argtypes = [ctypes.c_int, _D, ctypes.c_double, _D, _D, ctypes.c_int, ctypes.c_double, _D,
+                                      _D]
         L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         L.orc_moments.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_totals.argtypes = [ctypes.c_void_p, _D, _D]
@@ -122,6 +126,29 @@ def collide(q, f, tau, magic=3.0 / 16.0, F=(0.0, 0.0, 0.0), closure=CL_NONE, cs=
     out = np.zeros(q)
     tu = np.zeros(1)
     lib().orc_collide(q, _d(f), float(tau), float(magic), _d(F), int(closure), float(cs), _d(out), _d(tu))
+    return out, float(tu[0])
+
+
+MRT_DHUMIERES = (1.19, 1.4, 1.2, 1.4, 1.98)  # s_e, s_eps, s_q, s_pi, s_m
+
+
+def mrt_basis(q):
+    """Moment matrix M[q, q] and the rate group of every row."""
+    M = np.zeros((q, q))
+    g = np.zeros(q, dtype=np.int32)
+    if lib().orc_mrt_basis(q, _d(M), g.ctypes.data_as(_I)) != 0:
+        raise ValueError(q)
+    return M, g
+
+
+def collide_mrt(q, f, tau, rates=MRT_DHUMIERES, F=(0.0, 0.0, 0.0), closure=CL_NONE, cs=0.1):
+    f = _f64(f)
+    F = _f64(F)
+    r = _f64(rates)
+    out = np.zeros(q)
+    tu = np.zeros(1)
+    if lib().orc_collide_mrt(q, _d(f), float(tau), _d(r), _d(F), int(closure), float(cs), _d(out), _d(tu)) != 0:
+        raise ValueError("singular MRT basis")
     return out, float(tu[0])
 
 
@@ -226,6 +253,10 @@ class Sim:
         if h is not None and _lib is not None:
             _lib.orc_destroy(h)
             self._h = None
+
+    def set_mrt(self, rates=MRT_DHUMIERES):
+        if lib().orc_set_mrt(self._h, _d(_f64(rates))) != 0:
+            raise ValueError("singular MRT basis")
 
     def set_mlp(self, params, norm):
         lib().orc_set_mlp(self._h, _d(_f64(params)), _d(_f64(norm)))

@@ -102,6 +102,113 @@ static void guo_source(int q, const double *u, const double *F, double *S)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Multiple-relaxation-time (MRT) collision: relaxation in a moment space.   */
+/* The moments are polynomials of the lattice velocity; each moment relaxes   */
+/* toward the moment of f^eq with its own rate.                               */
+/*   D3Q19: the 19 polynomial moments 1, 19|c|^2-30, (21|c|^4-53|c|^2+24)/2,  */
+/*   c_a, (5|c|^2-9) c_a, 3c_x^2-|c|^2, (3|c|^2-5)(3c_x^2-|c|^2), c_y^2-c_z^2, */
+/*   (3|c|^2-5)(c_y^2-c_z^2), c_x c_y, c_y c_z, c_x c_z,                      */
+/*   (c_y^2-c_z^2) c_x, (c_z^2-c_x^2) c_y, (c_x^2-c_y^2) c_z.                 */
+/*   D3Q27: the 27 products T_a(c_x) T_b(c_y) T_c(c_z), T_0 = 1, T_1 = c,     */
+/*   T_2 = 3c^2 - 2.                                                          */
+/* Rate groups: 0 conserved density, 1 momentum (no effect with the Guo       */
+/* source), 2 viscous (second-order deviatoric moments, rate 1/tau),          */
+/* and the "ghost" groups 3 energy, 4 energy square, 5 heat flux q,           */
+/* 6 pi (fourth order), 7 m (third-order anti-symmetric).  Pinned by the      */
+/* orthogonality of the bases, the BGK and TRT special cases, conservation    */
+/* and the Poiseuille and Taylor-Green flows (tests).                         */
+/* ------------------------------------------------------------------------ */
+enum { G_RHO = 0, G_J = 1, G_NU = 2, G_E = 3, G_EPS = 4, G_Q = 5, G_PI = 6, G_M = 7 };
+
+static double mrt_moment19(int a, const int *c, int *group)
+{
+    double x = c[0], y = c[1], z = c[2], c2 = x * x + y * y + z * z;
+    switch (a) {
+    case 0: *group = G_RHO; return 1.0;
+    case 1: *group = G_E; return 19.0 * c2 - 30.0;
+    case 2: *group = G_EPS; return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    case 3: *group = G_J; return x;
+    case 4: *group = G_Q; return (5.0 * c2 - 9.0) * x;
+    case 5: *group = G_J; return y;
+    case 6: *group = G_Q; return (5.0 * c2 - 9.0) * y;
+    case 7: *group = G_J; return z;
+    case 8: *group = G_Q; return (5.0 * c2 - 9.0) * z;
+    case 9: *group = G_NU; return 3.0 * x * x - c2;
+    case 10: *group = G_PI; return (3.0 * c2 - 5.0) * (3.0 * x * x - c2);
+    case 11: *group = G_NU; return y * y - z * z;
+    case 12: *group = G_PI; return (3.0 * c2 - 5.0) * (y * y - z * z);
+    case 13: *group = G_NU; return x * y;
+    case 14: *group = G_NU; return y * z;
+    case 15: *group = G_NU; return x * z;
+    case 16: *group = G_M; return (y * y - z * z) * x;
+    case 17: *group = G_M; return (z * z - x * x) * y;
+    default: *group = G_M; return (x * x - y * y) * z;
+    }
+}
+
+static double cheb(int k, double c) { return k == 0 ? 1.0 : (k == 1 ? c : 3.0 * c * c - 2.0); }
+
+static double mrt_moment27(int a, const int *c, int *group)
+{
+    int kx = a % 3, ky = (a / 3) % 3, kz = a / 9;
+    int ones = (kx == 1) + (ky == 1) + (kz == 1), twos = (kx == 2) + (ky == 2) + (kz == 2);
+    int order = ones + 2 * twos;
+    if (order == 0) *group = G_RHO;
+    else if (order == 1) *group = G_J;
+    else if (order == 2) *group = G_NU;        /* c_a c_b and T_2(c_a) */
+    else if (order == 3) *group = G_Q;         /* c_a T_2(c_b), c_x c_y c_z */
+    else if (order == 4) *group = (ones == 0) ? G_E : G_PI;  /* T_2 T_2 ; c_a c_b T_2(c_c) */
+    else if (order == 5) *group = G_M;
+    else *group = G_EPS;                       /* T_2 T_2 T_2 */
+    return cheb(kx, c[0]) * cheb(ky, c[1]) * cheb(kz, c[2]);
+}
+
+/* Moment matrix M[a][i] and the rate group of each row; returns 0 on success. */
+int orc_mrt_basis(int q, double *M, int *groups)
+{
+    if (q != 19 && q != 27) return -1;
+    for (int a = 0; a < q; ++a)
+        for (int i = 0; i < q; ++i) {
+            int g;
+            M[a * q + i] = q == 19 ? mrt_moment19(a, VEL[i], &g) : mrt_moment27(a, VEL[i], &g);
+            groups[a] = g;
+        }
+    return 0;
+}
+
+/* Inverse of an n x n matrix by Gauss-Jordan elimination with partial     */
+/* pivoting; returns 0 on success, -1 if singular.                         */
+static int invert(int n, const double *A, double *Ainv)
+{
+    double W[27 * 54];
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < 2 * n; ++k) W[r * 2 * n + k] = k < n ? A[r * n + k] : (k - n == r ? 1.0 : 0.0);
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(W[r * 2 * n + col]) > fabs(W[piv * 2 * n + col])) piv = r;
+        if (fabs(W[piv * 2 * n + col]) < 1e-12) return -1;
+        if (piv != col)
+            for (int k = 0; k < 2 * n; ++k) {
+                double t = W[col * 2 * n + k];
+                W[col * 2 * n + k] = W[piv * 2 * n + k];
+                W[piv * 2 * n + k] = t;
+            }
+        double d = W[col * 2 * n + col];
+        for (int k = 0; k < 2 * n; ++k) W[col * 2 * n + k] /= d;
+        for (int r = 0; r < n; ++r) {
+            if (r == col) continue;
+            double f = W[r * 2 * n + col];
+            if (f == 0.0) continue;
+            for (int k = 0; k < 2 * n; ++k) W[r * 2 * n + k] -= f * W[col * 2 * n + k];
+        }
+    }
+    for (int r = 0; r < n; ++r)
+        for (int k = 0; k < n; ++k) Ainv[r * n + k] = W[r * 2 * n + n + k];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Closure parameters and the MLP (6 -> 32 -> 32 -> 1).                     */
 /* ------------------------------------------------------------------------ */
 enum { CL_NONE = 0, CL_SMAG = 1, CL_MLP = 2 };
@@ -304,6 +411,10 @@ typedef struct {
     double cs;
     double mlp[MLP_NPARAM];
     double norm[MLP_NNORM];
+    int collision;        /* 0 TRT, 1 MRT */
+    double mrt_rates[5];  /* ghost rates: energy, energy square, q, pi, m */
+    double Mm[27 * 27], Minv[27 * 27];
+    int mgroup[27];
     unsigned char *solid; /* NULL: all fluid */
     double *f, *g;        /* [q][n] canonical (post-stream, pre-collide) and scratch */
     int64_t fallbacks;    /* cells where the MLP closure fell back to Smagorinsky */
@@ -367,6 +478,18 @@ void orc_destroy(orc_sim *s)
     free(s->f);
     free(s->g);
     free(s);
+}
+
+/* Select the MRT collision with ghost rates {s_e, s_eps, s_q, s_pi, s_m};  */
+/* the viscous rate stays 1/tau (or the closure's).  Returns -1 if the      */
+/* basis is singular.                                                        */
+int orc_set_mrt(orc_sim *s, const double *rates)
+{
+    orc_mrt_basis(s->q, s->Mm, s->mgroup);
+    if (invert(s->q, s->Mm, s->Minv) != 0) return -1;
+    for (int k = 0; k < 5; ++k) s->mrt_rates[k] = rates[k];
+    s->collision = 1;
+    return 0;
 }
 
 void orc_set_mlp(orc_sim *s, const double *params, const double *norm)
@@ -462,6 +585,31 @@ static void collide_cell(const orc_sim *s, const double *f, double *fstar, doubl
             }
         }
     }
+    if (s->collision == 1) {
+        /* m_neq = M (f - feq), mS = M S; each moment a changes by           */
+        /* -s_a m_neq_a + (1 - s_a / 2) mS_a; back with M^-1.                */
+        double rate[8] = {0.0, 1.0, 1.0 / tau, s->mrt_rates[0], s->mrt_rates[1], s->mrt_rates[2],
+                          s->mrt_rates[3], s->mrt_rates[4]};
+        double dm[27];
+        for (int a = 0; a < q; ++a) {
+            double mn = 0.0, ms = 0.0;
+            for (int i = 0; i < q; ++i) {
+                mn += s->Mm[a * q + i] * (f[i] - feq[i]);
+                ms += s->Mm[a * q + i] * S[i];
+            }
+            double r = rate[s->mgroup[a]];
+            dm[a] = -r * mn + (1.0 - 0.5 * r) * ms;
+        }
+        for (int i = 0; i < q; ++i) {
+            double acc = 0.0;
+            for (int a = 0; a < q; ++a) acc += s->Minv[i * q + a] * dm[a];
+            fstar[i] = f[i] + acc;
+        }
+        if (u_out)
+            for (int a = 0; a < 3; ++a) u_out[a] = u[a];
+        if (tau_out) *tau_out = tau;
+        return;
+    }
     double wp = 1.0 / tau;
     double wm = 1.0 / (0.5 + s->magic / (tau - 0.5));
     for (int i = 0; i < q; ++i) {
@@ -489,6 +637,23 @@ void orc_collide(int q, const double *f, double tau, double magic, const double 
     s.closure = closure;
     s.cs = cs;
     collide_cell(&s, f, fstar, 0, tau_used, 0);
+}
+
+/* Collide a single cell with the MRT operator (rates as orc_set_mrt).     */
+int orc_collide_mrt(int q, const double *f, double tau, const double *rates, const double *F, int closure,
+                    double cs, double *fstar, double *tau_used)
+{
+    orc_sim s;
+    memset(&s, 0, sizeof s);
+    s.q = q;
+    s.tau = tau;
+    s.magic = 0.25;
+    for (int a = 0; a < 3; ++a) s.F[a] = F[a];
+    s.closure = closure;
+    s.cs = cs;
+    if (orc_set_mrt(&s, rates) != 0) return -1;
+    collide_cell(&s, f, fstar, 0, tau_used, 0);
+    return 0;
 }
 
 /* Non-equilibrium flux of one cell, packed xx,yy,zz,xy,xz,yz (for tests). */
