@@ -77,6 +77,18 @@ enum {
 /* Relaxation-time closures. */
 enum { LBM_LES_NONE = 0, LBM_LES_SMAGORINSKY = 1, LBM_LES_MLP = 2 };
 
+/* Collision operators (the collision Omega of Eq. (1)).
+ * TRT: two relaxation rates, 1/tau on the symmetric part of each pair of
+ *      opposite populations and 1/(1/2 + magic/(tau - 1/2)) on the
+ *      antisymmetric part (the paper's "Double Relaxation Time", Section 4).
+ * MRT: multiple relaxation times in a moment space (the collision of the
+ *      paper's LAGOON runs, Section 5.2): the second-order moments relax with
+ *      1/tau, the ghost moments with mrt_rates = {energy, energy square,
+ *      heat flux, fourth-order, third-order anti-symmetric}.  D3Q19 uses its
+ *      19 orthogonal polynomial moments, D3Q27 the tensor products of
+ *      {1, c, 3c^2 - 2}.  Not combinable with the learned closure. */
+enum { LBM_COLL_TRT = 0, LBM_COLL_MRT = 1 };
+
 typedef struct lbm_ctx lbm_ctx;
 
 typedef struct lbm_domain {
@@ -89,13 +101,16 @@ typedef struct lbm_domain {
     int32_t use_flags;       /* non-zero: reserve room for a per-cell solid mask */
     double magic;            /* TRT magic parameter Lambda (3/16 by default) */
     double cs_smag;          /* Smagorinsky constant (0.1 by default) */
+    int32_t collision;       /* LBM_COLL_* (TRT by default) */
+    double mrt_rates[5];     /* MRT ghost rates in (0, 2); default 1.19, 1.4, 1.2, 1.4, 1.98 */
     void *workspace;         /* device memory of workspace_bytes bytes, 256-byte aligned */
     size_t workspace_bytes;
     void *stream;            /* hipStream_t; NULL = the default stream */
 } lbm_domain;
 
 /* Fill *d with defaults: all faces periodic, rho_bc = 1, u_bc = 0, F32
- * storage, no closure, no flags, magic = 3/16, cs_smag = 0.1, no workspace. */
+ * storage, no closure, no flags, magic = 3/16, cs_smag = 0.1, TRT
+ * collision, MRT ghost rates {1.19, 1.4, 1.2, 1.4, 1.98}, no workspace. */
 void lbm_domain_defaults(lbm_domain *d);
 
 /* Bytes of device workspace a context needs for domain d and the stencil

@@ -37,6 +37,8 @@ class ClosureConfig:
     u_c: float = 0.05                # centre-line velocity of the start profile
     re_tau: float = 180.0            # friction Reynolds number setting the driving force
     noise: float = 0.05              # uniform velocity noise, fraction of u_c
+    vortical_rms: float = 0.0        # rms of a band-limited solenoidal perturbation (0: none)
+    vortical_wavelength: float = 32.0  # its peak wavelength in fine cells
     seed: int = 1234
     cs: float = 0.1                  # Smagorinsky constant (fallback and comparison)
     spinup: int = 2000               # fine steps before the first snapshot
@@ -74,6 +76,16 @@ def fine_lattice(cfg: ClosureConfig):
     tau_f = 0.5 + f * (cfg.tau_c - 0.5)
     lat = lbm.Lattice(cfg.fine, q=19, tau=tau_f, force=(cfg.force_c / f, 0.0, 0.0), bc=WALLS_Y)
     rho, u = inputs.channel(*cfg.fine, u_c=cfg.u_c, noise=cfg.noise, seed=cfg.seed)
+    if cfg.vortical_rms > 0:
+        torch = _torch()
+        nx, ny, nz = cfg.fine
+        up = inputs.vortical(nx, ny, nz, cfg.vortical_rms, cfg.vortical_wavelength, seed=cfg.seed + 1,
+                             device=lat.device)
+        # vanish at the walls (half a cell outside rows 0 and ny - 1)
+        y = torch.arange(ny, device=lat.device, dtype=torch.float32)
+        damp = (4.0 * (y + 0.5) * (ny - 0.5 - y) / (ny * ny)).view(1, 1, ny, 1)
+        u = torch.as_tensor(u, device=lat.device, dtype=torch.float64) + (up * damp).double()
+        del up
     lat.init_equilibrium(rho, u)
     return lat
 
@@ -197,6 +209,8 @@ def main(argv=None):
     ap.add_argument("--coarse", type=int, nargs=3, default=[256, 128, 128])
     ap.add_argument("--tau-c", type=float, default=0.503)
     ap.add_argument("--noise", type=float, default=0.3)
+    ap.add_argument("--vortical-rms", type=float, default=0.0)
+    ap.add_argument("--vortical-wavelength", type=float, default=32.0)
     ap.add_argument("--spinup", type=int, default=1000)
     ap.add_argument("--snapshots", type=int, default=4)
     ap.add_argument("--every", type=int, default=500)
@@ -206,7 +220,8 @@ def main(argv=None):
     ap.add_argument("--eval-coarse-steps", type=int, default=500)
     ap.add_argument("--out", default=None, help="write the JSON result here")
     a = ap.parse_args(argv)
-    cfg = ClosureConfig(coarse=tuple(a.coarse), tau_c=a.tau_c, noise=a.noise, spinup=a.spinup,
+    cfg = ClosureConfig(coarse=tuple(a.coarse), tau_c=a.tau_c, noise=a.noise, vortical_rms=a.vortical_rms,
+                        vortical_wavelength=a.vortical_wavelength, spinup=a.spinup,
                         snapshots=a.snapshots, every=a.every, train_steps=a.train_steps, batch=a.batch, lr=a.lr,
                         eval_coarse_steps=a.eval_coarse_steps)
 
@@ -215,7 +230,8 @@ def main(argv=None):
 
     log(f"[closure] fine {cfg.fine}, coarse {cfg.coarse}, tau_c {cfg.tau_c}, F_c {cfg.force_c:.3e}")
     res, P = study(cfg, log)
-    res["config"] = {k: getattr(cfg, k) for k in ("coarse", "factor", "tau_c", "u_c", "re_tau", "noise", "seed", "cs",
+    res["config"] = {k: getattr(cfg, k) for k in ("coarse", "factor", "tau_c", "u_c", "re_tau", "noise",
+                                                   "vortical_rms", "vortical_wavelength", "seed", "cs",
                                                    "spinup", "snapshots", "every", "train_steps", "batch", "lr",
                                                    "eval_coarse_steps")}
     res["config"]["fine"] = cfg.fine

@@ -9,6 +9,7 @@ namespace lbm {
 
 enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 enum { CL_NONE = 0, CL_SMAG = 1, CL_MLP = 2 };
+enum { COLL_TRT = 0, COLL_MRT = 1 };
 enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
 
 // Bit 31 of a cell's mask word marks the cell itself as solid; bit i
@@ -34,7 +35,9 @@ struct LatticeArgs {
     float F[3];
     float tau, magic, cs;    // molecular tau, TRT magic, Smagorinsky constant
     float omp, omm;          // omega+ and omega- of the molecular tau
+    float mrt[5];            // MRT ghost rates: energy, energy square, heat flux, fourth order, third order
     const float *mlp;        // closure parameters (device) or nullptr
+    const uint32_t *mlp_tab; // per-lane operand table of the closure network (device)
     unsigned long long *fallbacks;  // MLP fallback counter (device) or nullptr
 };
 
@@ -45,7 +48,7 @@ Launch lattice_launch(const LatticeArgs &a);
 
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, uint32_t *mask, hipStream_t s);
-hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int odd, hipStream_t s);
+hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
 hipError_t launch_init_eq(const LatticeArgs &a, int q, int st, const double *rho, const double *u, hipStream_t s);
 hipError_t launch_set_pdfs(const LatticeArgs &a, int q, int st, const double *f, hipStream_t s);
 hipError_t launch_get_pdfs(const LatticeArgs &a, int q, int st, int odd, double *f, hipStream_t s);
@@ -57,6 +60,8 @@ int totals_blocks();
 hipError_t launch_totals(const LatticeArgs &a, int q, int st, int odd, double *partial, double *final_out,
                          hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+// operand table of the closure network (71 x 64 words) from its parameters
+hipError_t launch_build_mlp_table(const float *params, uint32_t *table, hipStream_t s);
 
 // closure training path (lbm_closure.hip)
 hipError_t launch_box_filter4(int nx, int ny, int nz, const float *rho, const float *u, float *out, hipStream_t s);

@@ -7,7 +7,8 @@
 //   populations  q * n storage elements, [z][y][q][x] (rows of q direction segments)
 //   mask         n uint32 words (only with use_flags)
 //   totals       partial sums (1024 blocks x 5 doubles) and the final 5
-//   closure      MLP parameters (1313 + 24 FP32) and a fallback counter
+//   closure      MLP parameters (1313 + 24 FP32), their per-lane operand table
+//                (71 x 64 words) and a fallback counter
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -23,13 +24,14 @@ using namespace lbm;
 
 struct lbm_ctx {
     LatticeArgs a;
-    int q, st, cl;
+    int q, st, cl, coll;
     int64_t time;
     hipStream_t stream;
     char *ws;
     size_t ws_bytes;
     double *partial, *final_out;
     float *mlp;
+    uint32_t *mlp_tab;
     unsigned long long *fallbacks;
     uint32_t *mask;
     int64_t nfluid;
@@ -64,7 +66,7 @@ static int hip_fail(lbm_ctx *c, hipError_t e, const char *what)
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t pdf, mask, partial, final_out, mlp, fallback, total, pdf_bytes;
+    size_t pdf, mask, partial, final_out, mlp, mlp_tab, fallback, total, pdf_bytes;
 };
 
 static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c)
@@ -92,6 +94,8 @@ static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c)
     off += al256(5 * sizeof(double));
     L->mlp = off;
     off += al256((MLP_NPARAM + MLP_NNORM) * sizeof(float));
+    L->mlp_tab = off;
+    off += al256(71 * 64 * sizeof(uint32_t));
     L->fallback = off;
     off += 256;
     L->total = off;
@@ -112,6 +116,9 @@ void lbm_domain_defaults(lbm_domain *d)
     d->closure = LBM_LES_NONE;
     d->magic = 3.0 / 16.0;
     d->cs_smag = 0.1;
+    d->collision = LBM_COLL_TRT;
+    const double r[5] = {1.19, 1.4, 1.2, 1.4, 1.98};
+    for (int k = 0; k < 5; ++k) d->mrt_rates[k] = r[k];
 }
 
 int lbm_workspace_bytes(const lbm_domain *d, int stencil, size_t *out)
@@ -142,6 +149,14 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
         if ((d->bc[2 * a] == LBM_BC_PERIODIC) != (d->bc[2 * a + 1] == LBM_BC_PERIODIC))
             return fail(nullptr, LBM_EINVAL, "axis %d: a periodic face needs a periodic opposite face", a);
     if (flags && !d->use_flags) return fail(nullptr, LBM_EINVAL, "flags given but domain.use_flags is 0");
+    if (d->collision != LBM_COLL_TRT && d->collision != LBM_COLL_MRT)
+        return fail(nullptr, LBM_EINVAL, "unknown collision %d", d->collision);
+    if (d->collision == LBM_COLL_MRT) {
+        if (d->closure == LBM_LES_MLP) return fail(nullptr, LBM_EINVAL, "the MLP closure runs with TRT only");
+        for (int k = 0; k < 5; ++k)
+            if (!(d->mrt_rates[k] > 0.0 && d->mrt_rates[k] < 2.0))
+                return fail(nullptr, LBM_EINVAL, "mrt_rates[%d] must lie in (0, 2)", k);
+    }
     if (!d->workspace) return fail(nullptr, LBM_EINVAL, "workspace is NULL");
     if (((uintptr_t)d->workspace & 255) != 0) return fail(nullptr, LBM_EINVAL, "workspace must be 256-byte aligned");
     if (d->workspace_bytes < L.total)
@@ -156,6 +171,7 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     c->q = stencil;
     c->st = d->storage;
     c->cl = d->closure;
+    c->coll = d->collision;
     c->stream = (hipStream_t)d->stream;
     c->ws = (char *)d->workspace;
     c->ws_bytes = d->workspace_bytes;
@@ -188,7 +204,10 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     a.cs = (float)d->cs_smag;
     a.omp = (float)(1.0 / tau);
     a.omm = (float)(1.0 / (0.5 + d->magic / (tau - 0.5)));
+    for (int k = 0; k < 5; ++k) a.mrt[k] = (float)d->mrt_rates[k];
     a.mlp = c->mlp;
+    a.mlp_tab = (const uint32_t *)(c->ws + L.mlp_tab);
+    c->mlp_tab = (uint32_t *)(c->ws + L.mlp_tab);
     a.fallbacks = c->fallbacks;
 
     c->nfluid = (int64_t)a.n;
@@ -266,7 +285,7 @@ int lbm_step(lbm_ctx *c, int64_t n)
     if (c->cl == LBM_LES_MLP && !c->mlp_ready)
         return fail(c, LBM_ESTATE, "MLP closure selected but lbm_set_closure_weights was not called");
     for (int64_t k = 0; k < n; ++k) {
-        hipError_t e = launch_step(c->a, c->q, c->st, c->cl, (int)(c->time & 1), c->stream);
+        hipError_t e = launch_step(c->a, c->q, c->st, c->cl, c->coll, (int)(c->time & 1), c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "stream_collide launch");
         ++c->time;
     }
@@ -336,6 +355,7 @@ int lbm_set_closure_weights(lbm_ctx *c, const float *params, size_t n)
     for (int k = 0; k < 6; ++k)
         if (!(params[MLP_NPARAM + 6 + k] > 0.f)) return fail(c, LBM_EINVAL, "sigma[%d] must be > 0", k);
     HIPCHECK(c, hipMemcpyAsync(c->mlp, params, n * sizeof(float), hipMemcpyHostToDevice, c->stream), "weights");
+    HIPCHECK(c, launch_build_mlp_table(c->mlp, c->mlp_tab, c->stream), "weights table");
     HIPCHECK(c, hipStreamSynchronize(c->stream), "weights sync");
     c->mlp_ready = 1;
     return LBM_OK;

@@ -28,13 +28,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int P_W1 = 0, P_B1 = 192, P_W2 = 224, P_B2 = 1248, P_W3 = 1280, P_B3 = 1312;
 constexpr int P_MU = 1313, P_SG = 1319, P_LO = 1325, P_HI = 1331;
 
-__device__ inline uint16_t bf16_rne_bits(float v)
-{
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// FP32 -> bfloat16, round to nearest even (gfx950 converts in hardware)
+__device__ inline uint16_t bf16_rne_bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 
 __device__ inline float bf16_round(float v) { return __uint_as_float((uint32_t)bf16_rne_bits(v) << 16); }
 
@@ -66,6 +61,15 @@ __device__ inline float tanh_f(float x)
     const float e = __expf(-2.f * ax);
     const float t = copysignf((1.f - e) / (1.f + e), x);
     return ax < 0.1f ? p : t;
+}
+
+// tanh(x) = 1 - 2 / (1 + e^{2x}) with the hardware exp2 and reciprocal:
+// five instructions, absolute error ~1e-7 (below the bfloat16 rounding the
+// activations meet next); saturates correctly for large |x|.
+__device__ inline float tanh_fast(float x)
+{
+    const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);  // 2 log2(e)
+    return fmaf(-2.f, __builtin_amdgcn_rcpf(1.f + e), 1.f);
 }
 
 __device__ inline float softplus_f(float o) { return o > 20.f ? o : log1pf(__expf(o)); }
@@ -112,6 +116,100 @@ __device__ inline f32x16 bias16(const float *__restrict__ P, int off, int lane)
 #pragma unroll
     for (int r = 0; r < 16; ++r) c[r] = P[off + drow(r, lane)];
     return c;
+}
+
+// Per-lane operand table of a parameter block, built once per weight set
+// (lbm_set_closure_weights) and staged in LDS by the fused kernel: entry k of
+// lane l sits at T[k * 64 + l] (one coalesced 256-byte row per entry).
+//   k 0-1    A operand of layer 1 (4 bfloat16)
+//   k 2-9    A operands of layer 2, K-blocks 0-3 (4 bfloat16 each)
+//   k 10-25  b1 of the 16 accumulator rows of this lane
+//   k 26-41  b2 of the 16 accumulator rows
+//   k 42-57  W3 of the 16 accumulator rows, rounded to bfloat16
+//   k 58-63  mu, k 64-69 1/sigma, k 70 b3 (lane-uniform, replicated)
+constexpr int TAB_WORDS = 71;
+
+__device__ inline void build_table_lane(const float *__restrict__ P, int lane, uint32_t *__restrict__ T)
+{
+    auto put4 = [&](int k, bf16x4 v) {
+        T[k * 64 + lane] = (uint32_t)(uint16_t)v.x | ((uint32_t)(uint16_t)v.y << 16);
+        T[(k + 1) * 64 + lane] = (uint32_t)(uint16_t)v.z | ((uint32_t)(uint16_t)v.w << 16);
+    };
+    const int row = lane & 31, k0 = 4 * ((lane >> 5) & 1);
+    float w[4];
+    for (int t = 0; t < 4; ++t) w[t] = (k0 + t < 6) ? P[P_W1 + row * 6 + k0 + t] : 0.f;
+    put4(0, pack4(w[0], w[1], w[2], w[3]));
+    for (int kb = 0; kb < 4; ++kb) {
+        const float *q = P + P_W2 + row * 32 + 8 * kb + k0;
+        put4(2 + 2 * kb, pack4(q[0], q[1], q[2], q[3]));
+    }
+    for (int r = 0; r < 16; ++r) {
+        T[(10 + r) * 64 + lane] = __float_as_uint(P[P_B1 + drow(r, lane)]);
+        T[(26 + r) * 64 + lane] = __float_as_uint(P[P_B2 + drow(r, lane)]);
+        T[(42 + r) * 64 + lane] = __float_as_uint(bf16_round(P[P_W3 + drow(r, lane)]));
+    }
+    for (int k = 0; k < 6; ++k) {
+        T[(58 + k) * 64 + lane] = __float_as_uint(P[P_MU + k]);
+        T[(64 + k) * 64 + lane] = __float_as_uint(1.f / P[P_SG + k]);
+    }
+    T[70 * 64 + lane] = __float_as_uint(P[P_B3]);
+}
+
+__device__ inline bf16x4 tab4(const uint32_t *T, int k, int lane)
+{
+    const uint32_t lo = T[k * 64 + lane], hi = T[(k + 1) * 64 + lane];
+    bf16x4 r;
+    r.x = (short)(lo & 0xffffu);
+    r.y = (short)(lo >> 16);
+    r.z = (short)(hi & 0xffffu);
+    r.w = (short)(hi >> 16);
+    return r;
+}
+
+__device__ inline float tabf(const uint32_t *T, int k, int lane) { return __uint_as_float(T[k * 64 + lane]); }
+
+// Forward pass from the operand table (fused inference).  Returns o of this
+// lane's own sample.
+__device__ inline float mlp_forward_table(const uint32_t *T, const float (&x)[6], int lane)
+{
+    float z[6], zp[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) z[k] = (x[k] - tabf(T, 58 + k, lane)) * tabf(T, 64 + k, lane);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) zp[k] = __shfl_xor(z[k], 32, 64);
+    const bool hi = lane >= 32;
+    const bf16x4 b0 = hi ? pack4(zp[4], zp[5], 0.f, 0.f) : pack4(z[0], z[1], z[2], z[3]);
+    const bf16x4 b1 = hi ? pack4(z[4], z[5], 0.f, 0.f) : pack4(zp[0], zp[1], zp[2], zp[3]);
+    const bf16x4 a1 = tab4(T, 0, lane);
+    f32x16 c1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c1[r] = tabf(T, 10 + r, lane);
+    f32x16 h0 = mfma32(a1, b0, c1);
+    f32x16 h1 = mfma32(a1, b1, c1);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        h0[r] = tanh_fast(h0[r]);
+        h1[r] = tanh_fast(h1[r]);
+    }
+    f32x16 g0, g1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) g0[r] = g1[r] = tabf(T, 26 + r, lane);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        const bf16x4 a2 = tab4(T, 2 + 2 * kb, lane);
+        g0 = mfma32(a2, pack4(h0[4 * kb], h0[4 * kb + 1], h0[4 * kb + 2], h0[4 * kb + 3]), g0);
+        g1 = mfma32(a2, pack4(h1[4 * kb], h1[4 * kb + 1], h1[4 * kb + 2], h1[4 * kb + 3]), g1);
+    }
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float w = tabf(T, 42 + r, lane);
+        s0 += w * bf16_round(tanh_fast(g0[r]));
+        s1 += w * bf16_round(tanh_fast(g1[r]));
+    }
+    s0 += __shfl_xor(s0, 32, 64);
+    s1 += __shfl_xor(s1, 32, 64);
+    return (hi ? s1 : s0) + tabf(T, 70, lane);
 }
 
 // Forward pass.  h1_* and h2_* receive the FP32 activations of both blocks

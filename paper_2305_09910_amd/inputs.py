@@ -14,6 +14,8 @@ available, so these stand in for them with the stated shapes):
     shape of the paper's turbulent-channel benchmark.
   * Obstacles: random non-overlapping solid spheres filling a volume
     fraction -- a stand-in for the landing-gear geometry.
+  * Vortical perturbation: a band-limited divergence-free random field, the
+    start of the closure-training runs (energy at the filter scale).
 """
 from __future__ import annotations
 
@@ -115,3 +117,53 @@ def perturbation(shape, scale: float, seed: int):
     """Seeded i.i.d. uniform numbers in [-scale, scale] of the given shape."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-scale, scale, size=shape)
+
+
+def vortical(nx: int, ny: int, nz: int, rms: float, wavelength: float, seed: int = 7, kmax_factor: float = 3.0,
+             device=None):
+    """Seeded band-limited solenoidal velocity field, periodic on the box.
+
+    Fourier modes with |k| <= kmax_factor * k_p (k_p = 2 pi / wavelength)
+    get complex Gaussian amplitudes from numpy's PCG64(seed), drawn in a
+    fixed order over the mode cube, shaped to the energy spectrum
+    E(k) ~ k^4 exp(-2 (k/k_p)^2) and projected onto the plane normal to k
+    (divergence free); the field is the real inverse transform scaled to the
+    given rms velocity.  Returns float64 numpy [3, nz, ny, nx], or a float32
+    torch tensor on `device` (the inverse transform then runs there).
+    """
+    kp = 2 * math.pi / wavelength
+    kmax = kmax_factor * kp
+    mx = min(nx // 2, int(math.ceil(kmax * nx / (2 * math.pi))))
+    my = min(ny // 2, int(math.ceil(kmax * ny / (2 * math.pi))))
+    mz = min(nz // 2, int(math.ceil(kmax * nz / (2 * math.pi))))
+    ix = np.arange(0, mx + 1)                    # half spectrum along x
+    iy = np.r_[np.arange(0, my + 1), np.arange(-my, 0)]
+    iz = np.r_[np.arange(0, mz + 1), np.arange(-mz, 0)]
+    KZ, KY, KX = np.meshgrid(2 * math.pi * iz / nz, 2 * math.pi * iy / ny, 2 * math.pi * ix / nx, indexing="ij")
+    k = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.normal(size=(3,) + k.shape) + 1j * rng.normal(size=(3,) + k.shape)
+    kk = np.where(k > 0, k, 1.0)
+    kd = (a[0] * KX + a[1] * KY + a[2] * KZ) / kk ** 2
+    a = a - np.stack([KX, KY, KZ]) * kd  # solenoidal projection
+    amp = np.where((k > 0) & (k <= kmax), (k / kp) * np.exp(-(k / kp) ** 2), 0.0)  # |u_hat| ~ sqrt(E/k^2)
+    a = a * amp
+    zsel = np.r_[np.arange(0, mz + 1), np.arange(nz - mz, nz)]
+    ysel = np.r_[np.arange(0, my + 1), np.arange(ny - my, ny)]
+    if device is None:
+        full = np.zeros((3, nz, ny, nx // 2 + 1), dtype=np.complex128)
+        full[:, zsel[:, None, None], ysel[None, :, None], ix[None, None, :]] = a
+        u = np.fft.irfftn(full, s=(nz, ny, nx), axes=(1, 2, 3))
+        u *= rms / math.sqrt(np.mean(np.sum(u * u, axis=0)))
+        return u
+    import torch
+    spec = torch.zeros((3, nz, ny, nx // 2 + 1), dtype=torch.complex64, device=device)
+    zs = torch.as_tensor(zsel, device=device)
+    ys = torch.as_tensor(ysel, device=device)
+    xs = torch.as_tensor(ix, device=device)
+    spec[:, zs[:, None, None], ys[None, :, None], xs[None, None, :]] = torch.as_tensor(a.astype(np.complex64),
+                                                                                    device=device)
+    u = torch.fft.irfftn(spec, s=(nz, ny, nx), dim=(1, 2, 3))
+    del spec
+    u *= rms / torch.sqrt(torch.mean(torch.sum(u * u, dim=0)))
+    return u

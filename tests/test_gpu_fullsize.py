@@ -71,25 +71,30 @@ def _samples(shape, solid, n_random=1500, seed=0):
     return np.unique(cells)
 
 
-@pytest.mark.parametrize("name,storage", [
-    ("channel_256x128x128", "f32"),
-    ("channel_512x256x256", "f32"),
-    ("channel_512x256x256", "f16"),
-    ("channel_512x256x256", "bf16"),
-    ("obstacles_384_d3q27", "f32"),
+@pytest.mark.parametrize("name,storage,collision", [
+    ("channel_256x128x128", "f32", "trt"),
+    ("channel_512x256x256", "f32", "trt"),
+    ("channel_512x256x256", "f16", "trt"),
+    ("channel_512x256x256", "bf16", "trt"),
+    ("obstacles_384_d3q27", "f32", "trt"),
+    ("channel_512x256x256", "f32", "mrt"),
+    ("obstacles_384_d3q27", "f32", "mrt"),
 ])
-def test_two_steps_sampled_against_probe(name, storage):
+def test_two_steps_sampled_against_probe(name, storage, collision):
     from paper_2305_09910_amd import lbm
     cfg, rho, u = _case(name)
-    print(f"[case] {name} storage={storage}", flush=True)
+    print(f"[case] {name} storage={storage} collision={collision}", flush=True)
+    rates = (1.6, 1.75, 1.55, 1.65, 1.7) if cfg["q"] == 27 else oracle.MRT_DHUMIERES
     g = lbm.Lattice(cfg["shape"], q=cfg["q"], tau=cfg["tau"], force=cfg["force"], bc=cfg["bc"],
-                    u_bc=cfg["u_bc"], solid=cfg["solid"], storage=storage)
+                    u_bc=cfg["u_bc"], solid=cfg["solid"], storage=storage, collision=collision, mrt_rates=rates)
     g.init_equilibrium(rho, u)
     g.step(2)
     cells = _samples(cfg["shape"], cfg["solid"])
     got = g.gather(cells).cpu().numpy()
     o = oracle.Sim(cfg["q"], cfg["shape"], bc=tuple(BCS[b] for b in cfg["bc"]), tau=cfg["tau"], force=cfg["force"],
                    u_bc=cfg["u_bc"], solid=cfg["solid"])
+    if collision == "mrt":
+        o.set_mrt(rates)
     ref = o.probe(rho, u, 2, cells)
     c, w, _ = oracle.velocity_set(cfg["q"])
     err = np.abs(got - ref)

@@ -17,6 +17,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
+MRT27_RATES = (1.6, 1.75, 1.55, 1.65, 1.7)  # stable ghost rates of the D3Q27 tensor-product basis
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -39,14 +40,18 @@ BCS = {"periodic": oracle.BC_PERIODIC, "noslip": oracle.BC_NOSLIP, "velocity": o
 
 
 def pair(shape, q=19, tau=0.6, force=(0, 0, 0), bc=("periodic",) * 6, u_bc=None, rho_bc=None, solid=None,
-         storage="f32", closure="none", cs=0.1, magic=3 / 16):
+         storage="f32", closure="none", cs=0.1, magic=3 / 16, collision="trt", mrt_rates=None):
     """A GPU lattice and an oracle simulation with identical parameters."""
-    print(f"[case] q={q} shape={shape} bc={bc} storage={storage} closure={closure}", flush=True)
+    print(f"[case] q={q} shape={shape} bc={bc} storage={storage} closure={closure} collision={collision}",
+          flush=True)
     g = _lbm().Lattice(shape, q=q, tau=tau, force=force, bc=bc, u_bc=u_bc, rho_bc=rho_bc, solid=solid,
-                       storage=storage, closure=closure, cs=cs, magic=magic)
+                       storage=storage, closure=closure, cs=cs, magic=magic, collision=collision,
+                       mrt_rates=mrt_rates)
     cl = {"none": oracle.CL_NONE, "smagorinsky": oracle.CL_SMAG, "mlp": oracle.CL_MLP}[closure]
     o = oracle.Sim(q, shape, bc=tuple(BCS[b] for b in bc), tau=tau, magic=magic, force=force, u_bc=u_bc,
                    rho_bc=rho_bc, solid=solid, closure=cl, cs=cs)
+    if collision == "mrt":
+        o.set_mrt(oracle.MRT_DHUMIERES if mrt_rates is None else mrt_rates)
     return g, o
 
 
@@ -198,6 +203,58 @@ def test_smagorinsky_closure(q):
     err = max_rel(g.get_pdfs(), o.get_pdfs())
     print("smagorinsky err", err)
     assert err <= TOL32
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("closure", ["none", "smagorinsky"])
+def test_mrt_channel(q, closure):
+    """MRT collision, walled channel with force, 500 steps.  D3Q19 with the
+    d'Humieres ghost rates; D3Q27 (tensor-product basis) with ghost rates
+    >= 1.5 -- at tau = 0.53 its ghost rates near 1 diverge, on the oracle
+    as on the GPU."""
+    nx, ny, nz = 32, 24, 16
+    rates = None if q == 19 else MRT27_RATES
+    g, o = pair((nx, ny, nz), q=q, tau=0.53, force=(1e-6, 0, 0), closure=closure, collision="mrt",
+                mrt_rates=rates, bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"))
+    rho, u = inputs.channel(nx, ny, nz, 0.05, 0.1, seed=21)
+    g.init_equilibrium(rho, u)
+    o.init_equilibrium(rho, u)
+    g.step(500)
+    o.step(500)
+    err = max_rel(g.get_pdfs(), o.get_pdfs())
+    print("mrt channel err", err)
+    assert err <= TOL32
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_mrt_every_boundary_kind_and_solids(q):
+    shape = (20, 14, 10)
+    solid = np.zeros(shape[::-1], np.uint8)
+    solid[4:6, 6:9, 8:12] = 1
+    uw = np.zeros((6, 3))
+    uw[0] = (0.02, 0.0, 0.001)
+    uw[3] = (0.01, -0.002, 0.0)
+    bc = ("velocity", "pressure", "noslip", "velocity", "periodic", "periodic")
+    g, o = pair(shape, q=q, tau=0.7, force=(1e-5, 2e-6, -3e-6), bc=bc, u_bc=uw, solid=solid, collision="mrt",
+                mrt_rates=(1.1, 1.3, 1.25, 1.5, 1.7))
+    rho, u = inputs.uniform_flow(*shape, (0.01, 0.0, 0.0))
+    g.init_equilibrium(rho, u)
+    o.init_equilibrium(rho, u)
+    g.step(300)
+    o.step(300)
+    err = max_rel(g.get_pdfs(), o.get_pdfs(), solid)
+    print("mrt all-bc err", err)
+    assert err <= TOL32
+
+
+def test_mrt_rejects_mlp_and_bad_rates():
+    lbm = _lbm()
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.Lattice((16, 8, 8), collision="mrt", closure="mlp")
+    assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.Lattice((16, 8, 8), collision="mrt", mrt_rates=(1.0, 1.0, 2.0, 1.0, 1.0))
+    assert e.value.code == lbm.LBM_EINVAL
 
 
 # ---------------------------------------------------------------------------
