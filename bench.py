@@ -89,7 +89,7 @@ def profiled_traffic():
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    m = re.search(r"kernel source sha256\[:16\]: `([0-9a-f]+)`", txt)
+    m = re.search(r"kernel source sha256\[:16\]: `([0-9a-f]+)`", txt, re.I)
     t = re.search(r"HBM traffic per launch \(scaled\): ([0-9.]+) MB", txt)
     if not m or not t or m.group(1) != kernel_source_hash():
         return None
@@ -203,6 +203,30 @@ def cpu_baseline(cfg, budget_s=12.0):
                       f"({dt:.1f} s, OpenMP over z)"}
 
 
+FORMS = ["channel_512x256x256_f32", "channel_512x256x256_f16", "channel_512x256x256_bf16",
+         "obstacles_384^3_d3q27_f32", "channel_256x128x128_smagorinsky", "channel_256x128x128_mlp_closure",
+         "channel_512x256x256_mlp_closure", "channel_512x256x256_mrt", "obstacles_384^3_d3q27_mrt"]
+
+
+def form_cfg(key):
+    return {
+        "channel_512x256x256_f32": lambda: channel_cfg(512, 256, 256, "f32"),
+        "channel_512x256x256_f16": lambda: channel_cfg(512, 256, 256, "f16"),
+        "channel_512x256x256_bf16": lambda: channel_cfg(512, 256, 256, "bf16"),
+        "obstacles_384^3_d3q27_f32": lambda: obstacle_cfg(),
+        "channel_256x128x128_smagorinsky": lambda: channel_cfg(256, 128, 128, "f32", "smagorinsky"),
+        "channel_256x128x128_mlp_closure": lambda: channel_cfg(256, 128, 128, "f32", "mlp"),
+        "channel_512x256x256_mlp_closure": lambda: channel_cfg(512, 256, 256, "f32", "mlp"),
+        "channel_512x256x256_mrt": lambda: channel_cfg(512, 256, 256, "f32", collision="mrt"),
+        "obstacles_384^3_d3q27_mrt": lambda: obstacle_cfg(collision="mrt"),
+    }[key]()
+
+
+def form_plan():
+    for key in FORMS:
+        yield key, form_cfg(key)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +237,8 @@ def main():
     ap.add_argument("--form-steps", type=int, default=300)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB once with the library's copy kernel (counter calibration)")
+    ap.add_argument("--only-form", choices=FORMS, default=None,
+                    help="time only this form for --form-steps steps (for profiling); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the multi-GPU halo "
@@ -235,6 +261,13 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
 
+    if args.only_form:
+        log(f"[bench] form {args.only_form}, {args.form_steps} steps")
+        fr = time_lattice(form_cfg(args.only_form), args.form_steps, 50, diag_every=0)
+        log(f"[bench]   {fr['kernel_mlups']:.0f} MLUPS (kernel), {fr['achieved_gbs']:.0f} GB/s, "
+            f"kernel {fr['kernel_ms'] * 1e3:.1f} us")
+        return
+
     head = channel_cfg(256, 128, 128)
     log(f"[bench] headline {head['name']} f32, warmup {args.warmup}, steps {args.steps}")
     r = time_lattice(head, args.steps, args.warmup)
@@ -247,18 +280,7 @@ def main():
         bs = copy_bandwidth()
         log(f"[bench] device copy bandwidth {bs:.0f} GB/s")
         fs = args.form_steps
-        plan = [
-            ("channel_512x256x256_f32", channel_cfg(512, 256, 256, "f32")),
-            ("channel_512x256x256_f16", channel_cfg(512, 256, 256, "f16")),
-            ("channel_512x256x256_bf16", channel_cfg(512, 256, 256, "bf16")),
-            ("obstacles_384^3_d3q27_f32", obstacle_cfg()),
-            ("channel_256x128x128_smagorinsky", channel_cfg(256, 128, 128, "f32", "smagorinsky")),
-            ("channel_256x128x128_mlp_closure", channel_cfg(256, 128, 128, "f32", "mlp")),
-            ("channel_512x256x256_mlp_closure", channel_cfg(512, 256, 256, "f32", "mlp")),
-            ("channel_512x256x256_mrt", channel_cfg(512, 256, 256, "f32", collision="mrt")),
-            ("obstacles_384^3_d3q27_mrt", obstacle_cfg(collision="mrt")),
-        ]
-        for key, cfg in plan:
+        for key, cfg in form_plan():
             log(f"[bench] form {key}, {fs} steps")
             fr = time_lattice(cfg, fs, 50, diag_every=0)
             forms[key] = {"mlups": round(fr["mlups"], 1), "kernel_mlups": round(fr["kernel_mlups"], 1),
