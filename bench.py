@@ -68,8 +68,9 @@ def demo_closure_weights(seed=9):
     return np.concatenate([p, norm]).astype(np.float32)
 
 
-KERNEL_SOURCES = ["paper_2305_09910_amd/csrc/lbm_kernels.hip", "paper_2305_09910_amd/csrc/stencil.h",
-                  "paper_2305_09910_amd/csrc/internal.h", "paper_2305_09910_amd/csrc/mlp_wave.h"]
+KERNEL_SOURCES = ["paper_2305_09910_amd/csrc/lbm_kernels.hip", "paper_2305_09910_amd/csrc/lattice.h",
+                  "paper_2305_09910_amd/csrc/stencil.h", "paper_2305_09910_amd/csrc/internal.h",
+                  "paper_2305_09910_amd/csrc/mlp_wave.h"]
 PROFILE = "profiles/stream_collide_channel_256x128x128.md"
 
 
@@ -100,7 +101,8 @@ def make_lattice(cfg):
     from paper_2305_09910_amd import inputs, lbm
     lat = lbm.Lattice(cfg["shape"], q=cfg["q"], tau=cfg["tau"], force=cfg["force"], bc=cfg["bc"],
                       u_bc=cfg["u_bc"], solid=cfg["solid"], storage=cfg["storage"], closure=cfg["closure"],
-                      collision=cfg.get("collision", "trt"), mrt_rates=cfg.get("mrt_rates"))
+                      collision=cfg.get("collision", "trt"), mrt_rates=cfg.get("mrt_rates"),
+                      streaming=cfg.get("streaming", "aa"))
     if cfg["closure"] == "mlp":
         lat.set_closure_weights(demo_closure_weights())
     nx, ny, nz = cfg["shape"]
@@ -205,7 +207,9 @@ def cpu_baseline(cfg, budget_s=12.0):
 
 FORMS = ["channel_512x256x256_f32", "channel_512x256x256_f16", "channel_512x256x256_bf16",
          "obstacles_384^3_d3q27_f32", "channel_256x128x128_smagorinsky", "channel_256x128x128_mlp_closure",
-         "channel_512x256x256_mlp_closure", "channel_512x256x256_mrt", "obstacles_384^3_d3q27_mrt"]
+         "channel_512x256x256_mlp_closure", "channel_512x256x256_mrt", "obstacles_384^3_d3q27_mrt",
+         "channel_256x128x128_et", "channel_512x256x256_f32_et", "channel_512x256x256_f16_et",
+         "obstacles_384^3_d3q27_et"]
 
 
 def form_cfg(key):
@@ -219,6 +223,10 @@ def form_cfg(key):
         "channel_512x256x256_mlp_closure": lambda: channel_cfg(512, 256, 256, "f32", "mlp"),
         "channel_512x256x256_mrt": lambda: channel_cfg(512, 256, 256, "f32", collision="mrt"),
         "obstacles_384^3_d3q27_mrt": lambda: obstacle_cfg(collision="mrt"),
+        "channel_256x128x128_et": lambda: dict(channel_cfg(256, 128, 128, "f32"), streaming="et"),
+        "channel_512x256x256_f32_et": lambda: dict(channel_cfg(512, 256, 256, "f32"), streaming="et"),
+        "channel_512x256x256_f16_et": lambda: dict(channel_cfg(512, 256, 256, "f16"), streaming="et"),
+        "obstacles_384^3_d3q27_et": lambda: dict(obstacle_cfg(), streaming="et"),
     }[key]()
 
 

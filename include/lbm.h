@@ -9,9 +9,9 @@
  *     D3Q19 scheme of the LaBS section) with Guo body forcing,
  *   - halfway bounce-back walls, velocity and pressure faces, periodic faces,
  *     and an optional per-cell solid mask,
- *   - one population set kept in place in HBM (AA access pattern, the family
- *     of in-place schemes the paper's Esoteric Twist belongs to, Section 5.2),
- *     structure of arrays within each row of cells: [z][y][q][x],
+ *   - one population set kept in place in HBM, streamed with the AA access
+ *     pattern or with the Esoteric Twist the paper's LAGOON runs use
+ *     (Section 5.2), structure of arrays within each row of cells: [z][y][q][x],
  *   - optional LES closures (Smagorinsky, or a small learned MLP) that set a
  *     per-cell relaxation time.
  *
@@ -89,6 +89,18 @@ enum { LBM_LES_NONE = 0, LBM_LES_SMAGORINSKY = 1, LBM_LES_MLP = 2 };
  *      {1, c, 3c^2 - 2}.  Not combinable with the learned closure. */
 enum { LBM_COLL_TRT = 0, LBM_COLL_MRT = 1 };
 
+/* In-place streaming schemes (one population set in HBM; Section 5.2).
+ * AA: even steps read and write only the cell's own slots, odd steps read
+ *     from and write to the neighbours x -+ c_i.
+ * ET: the Esoteric Twist: every step reads f_i at x + max(-c_i, 0) and
+ *     writes at x + max(c_i, 0), the slot of a direction alternating between
+ *     i and opposite(i) from step to step.  Each non-periodic axis gets one
+ *     ghost layer beyond its + face in the store (it holds the populations
+ *     that face returns).  Not combinable with the learned closure.
+ * Both give the same populations up to FP32 rounding order (none: the same
+ * arithmetic runs on the same values). */
+enum { LBM_STREAM_AA = 0, LBM_STREAM_ET = 1 };
+
 typedef struct lbm_ctx lbm_ctx;
 
 typedef struct lbm_domain {
@@ -103,6 +115,7 @@ typedef struct lbm_domain {
     double cs_smag;          /* Smagorinsky constant (0.1 by default) */
     int32_t collision;       /* LBM_COLL_* (TRT by default) */
     double mrt_rates[5];     /* MRT ghost rates in (0, 2); default 1.19, 1.4, 1.2, 1.4, 1.98 */
+    int32_t streaming;       /* LBM_STREAM_* (AA by default) */
     void *workspace;         /* device memory of workspace_bytes bytes, 256-byte aligned */
     size_t workspace_bytes;
     void *stream;            /* hipStream_t; NULL = the default stream */
@@ -110,11 +123,13 @@ typedef struct lbm_domain {
 
 /* Fill *d with defaults: all faces periodic, rho_bc = 1, u_bc = 0, F32
  * storage, no closure, no flags, magic = 3/16, cs_smag = 0.1, TRT
- * collision, MRT ghost rates {1.19, 1.4, 1.2, 1.4, 1.98}, no workspace. */
+ * collision, MRT ghost rates {1.19, 1.4, 1.2, 1.4, 1.98}, AA streaming, no
+ * workspace. */
 void lbm_domain_defaults(lbm_domain *d);
 
 /* Bytes of device workspace a context needs for domain d and the stencil
- * (19 or 27).  Only nx, ny, nz, storage, closure and use_flags are read. */
+ * (19 or 27).  Only nx, ny, nz, storage, closure, use_flags, streaming and
+ * (for the ghost layers of the Esoteric Twist) bc are read. */
 int lbm_workspace_bytes(const lbm_domain *d, int stencil, size_t *out);
 
 /*

@@ -27,6 +27,9 @@ struct LatticeArgs {
     const uint32_t *mask;    // [n] or nullptr
     int nx, ny, nz;
     uint32_t n;              // cells
+    int sx, sy;              // cells per stored row and rows per stored plane: nx, ny, or one more
+                             // for the ghost layer of the Esoteric Twist on a non-periodic + face
+    int et;                  // streaming scheme: 0 AA pattern, 1 Esoteric Twist
     int per[3];              // axis periodic?
     int bc[6];               // face kinds
     int any_vp;              // any velocity / pressure face
@@ -49,6 +52,8 @@ Launch lattice_launch(const LatticeArgs &a);
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, uint32_t *mask, hipStream_t s);
 hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
+// Esoteric Twist step (lbm_et.hip); no learned closure
+hipError_t launch_step_et(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
 hipError_t launch_init_eq(const LatticeArgs &a, int q, int st, const double *rho, const double *u, hipStream_t s);
 hipError_t launch_set_pdfs(const LatticeArgs &a, int q, int st, const double *f, hipStream_t s);
 hipError_t launch_get_pdfs(const LatticeArgs &a, int q, int st, int odd, double *f, hipStream_t s);

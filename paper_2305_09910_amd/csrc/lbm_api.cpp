@@ -4,7 +4,9 @@
 // caller's stream.  The library allocates no device memory: everything lives
 // in the caller's workspace.  Layout of the workspace (each part 256-byte
 // aligned):
-//   populations  q * n storage elements, [z][y][q][x] (rows of q direction segments)
+//   populations  q * n storage elements, [z][y][q][x] (rows of q direction segments);
+//                with the Esoteric Twist each non-periodic axis has one more
+//                cell (the ghost layer beyond its + face)
 //   mask         n uint32 words (only with use_flags)
 //   totals       partial sums (1024 blocks x 5 doubles) and the final 5
 //   closure      MLP parameters (1313 + 24 FP32), their per-lane operand table
@@ -67,6 +69,7 @@ static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
     size_t pdf, mask, partial, final_out, mlp, mlp_tab, fallback, total, pdf_bytes;
+    int sx, sy, sz;  // cells of the population store per axis
 };
 
 static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c)
@@ -79,12 +82,26 @@ static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c)
         return fail(c, LBM_EINVAL, "unknown storage %d", d->storage);
     if (d->closure < LBM_LES_NONE || d->closure > LBM_LES_MLP)
         return fail(c, LBM_EINVAL, "unknown closure %d", d->closure);
+    if (d->streaming != LBM_STREAM_AA && d->streaming != LBM_STREAM_ET)
+        return fail(c, LBM_EINVAL, "unknown streaming scheme %d", d->streaming);
     const uint64_t n = (uint64_t)d->nx * (uint64_t)d->ny * (uint64_t)d->nz;
     if (n >= (1ull << 31)) return fail(c, LBM_ENOMEM, "domain of %llu cells exceeds 2^31 cells", (unsigned long long)n);
+    const bool et = d->streaming == LBM_STREAM_ET;
     const size_t elem = d->storage == LBM_STORE_F32 ? 4 : 2;
+    // Row pitch: whole 128-byte lines, so that every direction segment
+    // starts on a line (the ghost column of the Esoteric Twist would
+    // otherwise shift all rows); the padding is never accessed.
+    const int line = (int)(128 / elem);
+    const int rx = d->nx + (et && d->bc[0] != LBM_BC_PERIODIC);
+    L->sx = (rx + line - 1) / line * line;
+    L->sy = d->ny + (et && d->bc[2] != LBM_BC_PERIODIC);
+    L->sz = d->nz + (et && d->bc[4] != LBM_BC_PERIODIC);
+    const uint64_t ns = (uint64_t)L->sx * (uint64_t)L->sy * (uint64_t)L->sz;
+    if (ns >= (1ull << 31))
+        return fail(c, LBM_ENOMEM, "store of %llu cells exceeds 2^31 cells", (unsigned long long)ns);
     size_t off = 0;
     L->pdf = off;
-    L->pdf_bytes = (size_t)q * n * elem;
+    L->pdf_bytes = (size_t)q * ns * elem;
     off += al256(L->pdf_bytes);
     L->mask = off;
     if (d->use_flags) off += al256(4 * n);
@@ -151,6 +168,8 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     if (flags && !d->use_flags) return fail(nullptr, LBM_EINVAL, "flags given but domain.use_flags is 0");
     if (d->collision != LBM_COLL_TRT && d->collision != LBM_COLL_MRT)
         return fail(nullptr, LBM_EINVAL, "unknown collision %d", d->collision);
+    if (d->streaming == LBM_STREAM_ET && d->closure == LBM_LES_MLP)
+        return fail(nullptr, LBM_EINVAL, "the learned closure runs with AA streaming only");
     if (d->collision == LBM_COLL_MRT) {
         if (d->closure == LBM_LES_MLP) return fail(nullptr, LBM_EINVAL, "the MLP closure runs with TRT only");
         for (int k = 0; k < 5; ++k)
@@ -190,6 +209,9 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     a.ny = d->ny;
     a.nz = d->nz;
     a.n = (uint32_t)((uint64_t)d->nx * d->ny * d->nz);
+    a.sx = L.sx;
+    a.sy = L.sy;
+    a.et = d->streaming == LBM_STREAM_ET;
     for (int k = 0; k < 3; ++k) a.per[k] = d->bc[2 * k] == LBM_BC_PERIODIC;
     a.any_vp = 0;
     for (int f = 0; f < 6; ++f) {
@@ -285,7 +307,9 @@ int lbm_step(lbm_ctx *c, int64_t n)
     if (c->cl == LBM_LES_MLP && !c->mlp_ready)
         return fail(c, LBM_ESTATE, "MLP closure selected but lbm_set_closure_weights was not called");
     for (int64_t k = 0; k < n; ++k) {
-        hipError_t e = launch_step(c->a, c->q, c->st, c->cl, c->coll, (int)(c->time & 1), c->stream);
+        const int odd = (int)(c->time & 1);
+        hipError_t e = c->a.et ? launch_step_et(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream)
+                               : launch_step(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "stream_collide launch");
         ++c->time;
     }

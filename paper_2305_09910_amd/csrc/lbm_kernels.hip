@@ -29,572 +29,9 @@
 // written once per step); no matrix cores are used here.  All arithmetic is
 // FP32 on deviations, which keeps small forcing increments above the FP32
 // rounding of w_i.
-#include <hip/hip_runtime.h>
-#include <math.h>
-#include <stdint.h>
-
-#include <algorithm>
-#include <type_traits>
-
-#include "internal.h"
-#include "mlp_wave.h"
-#include "stencil.h"
-
-// Tuning knobs: the minimum number of waves per SIMD the register
-// allocation must allow for the stream-collide kernel, the workgroup size,
-// and the streaming (nontemporal) hints of the plain path (1: measured
-// policy, 0: none, 2: everywhere).
-#ifndef LBM_MIN_WAVES
-#define LBM_MIN_WAVES 1
-#endif
-#ifndef LBM_BLOCK
-#define LBM_BLOCK 256
-#endif
-// whole rows of up to LBM_ROW_MAX cells per workgroup (0: fixed LBM_BLOCK)
-#ifndef LBM_ROW_MAX
-#define LBM_ROW_MAX 0
-#endif
-#define LBM_LB_THREADS (LBM_ROW_MAX > LBM_BLOCK ? LBM_ROW_MAX : LBM_BLOCK)
-#ifndef LBM_NT_POLICY
-#define LBM_NT_POLICY 1
-#endif
-// Code paths of the stream-collide kernel.  Unified: one path for every
-// cell, cut links handled by address selects (no divergence between cells
-// next to faces or solids and open cells).  Split: a plain path for cells
-// away from non-periodic faces and a separate boundary path.  Measured on
-// MI355X: unified is faster for FP32 storage (+3% on 512x256x256) and for
-// masked domains (+6% on the 384^3 D3Q27 obstacles); split is faster for
-// 16-bit storage (+14%) and with the MLP closure (+5%).
-// LBM_UNIFIED: 0 split, 1 unified, 2 the measured choice per instantiation.
-#ifndef LBM_UNIFIED
-#define LBM_UNIFIED 2
-#endif
+#include "lattice.h"
 
 namespace lbm {
-
-// Streaming hints.  A population line that only this wavefront touches is
-// loaded and stored with the nontemporal hint (no reuse; it should not
-// displace other lines).  Lines read with a +-1 shift along x are shared
-// with the neighbouring wavefront in the same workgroup, so those keep the
-// normal policy and meet in L2.
-template <bool NT, class T>
-__device__ inline T ld_pop(const T *p)
-{
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    return *p;
-}
-
-template <bool NT, class T>
-__device__ inline void st_pop(T *p, T v)
-{
-    if constexpr (NT)
-        __builtin_nontemporal_store(v, p);
-    else
-        *p = v;
-}
-
-// hint for a population access along direction i on the even (local) or
-// odd (shifted) step of the plain path
-template <int I>
-struct Hint {
-    static constexpr bool even = LBM_NT_POLICY != 0;
-    static constexpr bool odd = LBM_NT_POLICY == 2 || (LBM_NT_POLICY == 1 && cdir(I, 0) == 0);
-};
-
-// ---------------------------------------------------------------------------
-// storage formats
-// ---------------------------------------------------------------------------
-template <int ST>
-struct Store;
-
-template <>
-struct Store<ST_F32> {
-    using T = float;
-    template <bool NT = false>
-    __device__ static float ld(const T *p) { return ld_pop<NT>(p); }
-    template <bool NT = false>
-    __device__ static void st(T *p, float v) { st_pop<NT>(p, v); }
-    __device__ static T cvt(float v) { return v; }
-};
-
-template <>
-struct Store<ST_F16> {
-    using T = _Float16;
-    template <bool NT = false>
-    __device__ static float ld(const T *p) { return (float)ld_pop<NT>(p); }
-    template <bool NT = false>
-    __device__ static void st(T *p, float v) { st_pop<NT>(p, (_Float16)v); }
-    __device__ static T cvt(float v) { return (_Float16)v; }
-};
-
-// bfloat16 as raw bits: widen by a shift, narrow with the hardware
-// round-to-nearest-even conversion
-__device__ inline uint16_t f32_to_bf16_rne(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
-
-template <>
-struct Store<ST_BF16> {
-    using T = uint16_t;
-    template <bool NT = false>
-    __device__ static float ld(const T *p) { return __uint_as_float((uint32_t)ld_pop<NT>(p) << 16); }
-    template <bool NT = false>
-    __device__ static void st(T *p, float v) { st_pop<NT>(p, f32_to_bf16_rne(v)); }
-    __device__ static T cvt(float v) { return f32_to_bf16_rne(v); }
-};
-
-// ---------------------------------------------------------------------------
-// cell geometry
-// ---------------------------------------------------------------------------
-struct Geom {
-    int x, y, z;
-    uint32_t c;    // cell index (z ny + y) nx + x of fields and the mask
-    uint32_t row;  // row index z ny + y of the population store
-    int xm, xp, ym, yp, zm, zp;    // wrapped neighbour coordinates
-    bool cxl, cxh, cyl, cyh, czl, czh;  // link through that face is cut by a non-periodic face
-};
-
-__device__ inline Geom make_geom(const LatticeArgs &a, int x, int y, int z)
-{
-    Geom g;
-    g.x = x;
-    g.y = y;
-    g.z = z;
-    g.row = (uint32_t)z * (uint32_t)a.ny + (uint32_t)y;
-    g.c = g.row * (uint32_t)a.nx + (uint32_t)x;
-    g.xm = x == 0 ? a.nx - 1 : x - 1;
-    g.xp = x == a.nx - 1 ? 0 : x + 1;
-    g.ym = y == 0 ? a.ny - 1 : y - 1;
-    g.yp = y == a.ny - 1 ? 0 : y + 1;
-    g.zm = z == 0 ? a.nz - 1 : z - 1;
-    g.zp = z == a.nz - 1 ? 0 : z + 1;
-    g.cxl = !a.per[0] && x == 0;
-    g.cxh = !a.per[0] && x == a.nx - 1;
-    g.cyl = !a.per[1] && y == 0;
-    g.cyh = !a.per[1] && y == a.ny - 1;
-    g.czl = !a.per[2] && z == 0;
-    g.czh = !a.per[2] && z == a.nz - 1;
-    return g;
-}
-
-// index of the neighbour at offset (dx, dy, dz), periodic wrap
-__device__ inline uint32_t nbr(const LatticeArgs &a, const Geom &g, int dx, int dy, int dz)
-{
-    const int xx = dx < 0 ? g.xm : (dx > 0 ? g.xp : g.x);
-    const int yy = dy < 0 ? g.ym : (dy > 0 ? g.yp : g.y);
-    const int zz = dz < 0 ? g.zm : (dz > 0 ? g.zp : g.z);
-    return ((uint32_t)zz * (uint32_t)a.ny + (uint32_t)yy) * (uint32_t)a.nx + (uint32_t)xx;
-}
-
-// Population store: rows of q direction segments, [z][y][i][x].  Each
-// segment holds the nx populations of one direction of one row, so a
-// wavefront's accesses for one direction are contiguous, and the q segments
-// of a row sit together (one block of q nx elements per row).
-template <int Q>
-__device__ inline uint64_t pidx(const LatticeArgs &a, int i, uint32_t row, int x)
-{
-    return ((uint64_t)row * Q + (uint64_t)i) * (uint32_t)a.nx + (uint32_t)x;
-}
-
-// row and x of the neighbour at offset (dx, dy, dz), periodic wrap
-__device__ inline uint32_t nbr_row(const LatticeArgs &a, const Geom &g, int dy, int dz)
-{
-    const int yy = dy < 0 ? g.ym : (dy > 0 ? g.yp : g.y);
-    const int zz = dz < 0 ? g.zm : (dz > 0 ? g.zp : g.z);
-    return (uint32_t)zz * (uint32_t)a.ny + (uint32_t)yy;
-}
-
-__device__ inline int nbr_x(const Geom &g, int dx) { return dx < 0 ? g.xm : (dx > 0 ? g.xp : g.x); }
-
-template <int Q>
-__device__ inline uint64_t pidx_nbr(const LatticeArgs &a, const Geom &g, int i, int dx, int dy, int dz)
-{
-    return pidx<Q>(a, i, nbr_row(a, g, dy, dz), nbr_x(g, dx));
-}
-
-// does the link from this cell along (dx, dy, dz) leave through a non-periodic face?
-__device__ inline bool face_cut(const Geom &g, int dx, int dy, int dz)
-{
-    return (dx < 0 && g.cxl) || (dx > 0 && g.cxh) || (dy < 0 && g.cyl) || (dy > 0 && g.cyh) ||
-           (dz < 0 && g.czl) || (dz > 0 && g.czh);
-}
-
-// Face that decides a cut link along (dx, dy, dz): among the crossed
-// non-periodic faces the first of no-slip, velocity, pressure (lowest face
-// index among equals).  Returns -1 when no face is crossed.
-__device__ inline int deciding_face(const LatticeArgs &a, const Geom &g, int dx, int dy, int dz)
-{
-    int best = -1, rank = 0;
-    const bool cross[6] = {dx < 0 && g.cxl, dx > 0 && g.cxh, dy < 0 && g.cyl,
-                           dy > 0 && g.cyh, dz < 0 && g.czl, dz > 0 && g.czh};
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        if (!cross[f]) continue;
-        const int k = a.bc[f];
-        const int r = k == BC_NOSLIP ? 3 : (k == BC_VELOCITY ? 2 : (k == BC_PRESSURE ? 1 : 0));
-        if (r > rank) {
-            rank = r;
-            best = f;
-        }
-    }
-    return best;
-}
-
-// ---------------------------------------------------------------------------
-// canonical read (shared by the step kernel and every state reader)
-// ---------------------------------------------------------------------------
-template <int Q, int ST>
-__device__ inline void load_canonical(const LatticeArgs &a, const Geom &g, uint32_t m, int odd, float (&d)[Q])
-{
-    using S = Store<ST>;
-    const typename S::T *A = (const typename S::T *)a.pdf;
-    if (!odd) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = S::ld(A + pidx<Q>(a, i, g.row, g.x));
-    } else {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
-            // source x - c_i; blocked when that link is cut (mask bit of opposite(i))
-            const bool cut = face_cut(g, -dx, -dy, -dz) || ((m >> opp(i)) & 1u);
-            const uint64_t own = pidx<Q>(a, i, g.row, g.x);
-            const uint64_t src = pidx_nbr<Q>(a, g, opp(i), -dx, -dy, -dz);
-            d[i] = S::ld(A + (cut ? own : src));
-        }
-    }
-}
-
-// Compile-time loop over the directions (so each access can take its own
-// streaming hint).
-template <int I, int Q, class F>
-__device__ inline void for_dirs(F &&f)
-{
-    if constexpr (I < Q) {
-        f(std::integral_constant<int, I>{});
-        for_dirs<I + 1, Q>(f);
-    }
-}
-
-// Read of a cell none of whose links crosses a non-periodic face: no face
-// logic.  Links cut by a solid neighbour (mask bit of the link) only matter
-// on the odd step, where they select the cell's own slot instead of the
-// neighbour's -- a per-direction select, not a branch, so wavefronts that
-// mix cells next to solids with open cells do not diverge.
-template <int Q, int ST, bool MASK>
-__device__ inline void load_plain(const LatticeArgs &a, const Geom &g, uint32_t m, int odd, float (&d)[Q])
-{
-    using S = Store<ST>;
-    const typename S::T *A = (const typename S::T *)a.pdf;
-    if (!odd) {
-        const typename S::T *R = A + pidx<Q>(a, 0, g.row, g.x);
-        for_dirs<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            d[i] = S::template ld<Hint<i>::even>(R + (uint64_t)i * (uint32_t)a.nx);
-        });
-    } else {
-        for_dirs<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            uint64_t k = pidx_nbr<Q>(a, g, opp(i), -cdir(i, 0), -cdir(i, 1), -cdir(i, 2));
-            if constexpr (MASK) {
-                if (i != 0 && ((m >> opp(i)) & 1u)) k = pidx<Q>(a, i, g.row, g.x);
-            }
-            d[i] = S::template ld<Hint<i>::odd>(A + k);
-        });
-    }
-}
-
-template <int Q, int ST, bool MASK>
-__device__ inline void store_plain(const LatticeArgs &a, const Geom &g, uint32_t m, int odd, const float (&d)[Q])
-{
-    using S = Store<ST>;
-    typename S::T *A = (typename S::T *)a.pdf;
-    if (!odd) {
-        typename S::T *R = A + pidx<Q>(a, 0, g.row, g.x);
-        for_dirs<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            S::template st<Hint<i>::even>(R + (uint64_t)opp(i) * (uint32_t)a.nx, d[i]);
-        });
-    } else {
-        for_dirs<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            uint64_t k = pidx_nbr<Q>(a, g, i, cdir(i, 0), cdir(i, 1), cdir(i, 2));
-            if constexpr (MASK) {
-                if (i != 0 && ((m >> i) & 1u)) k = pidx<Q>(a, opp(i), g.row, g.x);
-            }
-            S::template st<Hint<i>::odd>(A + k, d[i]);
-        });
-    }
-}
-
-// ---------------------------------------------------------------------------
-// collision: TRT + Guo on deviations, optional Smagorinsky relaxation time
-// ---------------------------------------------------------------------------
-struct Macro {
-    float rho, ux, uy, uz;
-};
-
-template <int Q>
-__device__ inline Macro moments(const LatticeArgs &a, const float (&d)[Q], float &drho)
-{
-    float s = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        s += d[i];
-        if (cdir(i, 0)) jx += cdir(i, 0) > 0 ? d[i] : -d[i];
-        if (cdir(i, 1)) jy += cdir(i, 1) > 0 ? d[i] : -d[i];
-        if (cdir(i, 2)) jz += cdir(i, 2) > 0 ? d[i] : -d[i];
-    }
-    drho = s;
-    Macro M;
-    M.rho = 1.f + s;
-    const float ir = 1.f / M.rho;
-    M.ux = (jx + 0.5f * a.F[0]) * ir;
-    M.uy = (jy + 0.5f * a.F[1]) * ir;
-    M.uz = (jz + 0.5f * a.F[2]) * ir;
-    return M;
-}
-
-// Non-equilibrium momentum flux with the forcing correction,
-// P_c = sum_i c_i c_i (f_i - f_i^eq) + (u F + F u)/2, packed xx,yy,zz,xy,xz,yz.
-// With deviations, sum_i c c f^eq - sum_i c c w = drho/3 I + rho u u.
-template <int Q>
-__device__ inline void noneq_flux(const LatticeArgs &a, const float (&d)[Q], float drho, const Macro &M,
-                                  float (&P)[6])
-{
-    float pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pxz = 0.f, pyz = 0.f;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const int cx = cdir(i, 0), cy = cdir(i, 1), cz = cdir(i, 2);
-        if (cx) pxx += d[i];
-        if (cy) pyy += d[i];
-        if (cz) pzz += d[i];
-        if (cx * cy) pxy += cx * cy > 0 ? d[i] : -d[i];
-        if (cx * cz) pxz += cx * cz > 0 ? d[i] : -d[i];
-        if (cy * cz) pyz += cy * cz > 0 ? d[i] : -d[i];
-    }
-    const float third = drho * (1.f / 3.f);
-    const float F0 = a.F[0], F1 = a.F[1], F2 = a.F[2];
-    P[0] = pxx - third - M.rho * M.ux * M.ux + M.ux * F0;
-    P[1] = pyy - third - M.rho * M.uy * M.uy + M.uy * F1;
-    P[2] = pzz - third - M.rho * M.uz * M.uz + M.uz * F2;
-    P[3] = pxy - M.rho * M.ux * M.uy + 0.5f * (M.ux * F1 + F0 * M.uy);
-    P[4] = pxz - M.rho * M.ux * M.uz + 0.5f * (M.ux * F2 + F0 * M.uz);
-    P[5] = pyz - M.rho * M.uy * M.uz + 0.5f * (M.uy * F2 + F1 * M.uz);
-}
-
-__device__ inline float flux_norm(const float (&P)[6])
-{
-    return sqrtf(P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + 2.f * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]));
-}
-
-// Hou et al. (1996) Smagorinsky relaxation time from |P_c|:
-// tau_s = (tau + sqrt(tau^2 + a)) / 2 with a = 18 sqrt(2) Cs^2 |P_c| / rho.
-// Returned as the excess tau_s - tau = (a/2) / (sqrt(tau^2 + a) + tau), which
-// has no cancellation in FP32 when a << tau^2.
-__device__ inline float smag_excess(float tau, float cs, float Qn, float rho)
-{
-    const float a = 18.f * 1.41421356237f * cs * cs * Qn / rho;
-    return 0.5f * a / (sqrtf(tau * tau + a) + tau);
-}
-
-// keep: exchange each pair instead of colliding (solid lanes on the even
-// step, which store direction i into slot opposite(i) and so put every
-// slot's own value back; see the stream-collide kernel)
-template <int Q>
-__device__ inline void trt_collide(const LatticeArgs &a, float (&d)[Q], float drho, const Macro &M, float wp,
-                                   float wm, bool keep = false)
-{
-    const float F0 = a.F[0], F1 = a.F[1], F2 = a.F[2];
-    const float usq = M.ux * M.ux + M.uy * M.uy + M.uz * M.uz;
-    const float uF = M.ux * F0 + M.uy * F1 + M.uz * F2;
-    const float kp = 1.f - 0.5f * wp, km = 1.f - 0.5f * wm;
-    const float base = drho - 1.5f * M.rho * usq;  // shared part of the symmetric equilibrium
-    {
-        constexpr float w0 = (float)wgt<Q>(0);
-        const float deq = w0 * base;
-        const float S = w0 * (-3.f * uF);
-        d[0] = keep ? d[0] : d[0] - wp * (d[0] - deq) + kp * S;
-    }
-#pragma unroll
-    for (int i = 1; i < Q; i += 2) {
-        const int cx = cdir(i, 0), cy = cdir(i, 1), cz = cdir(i, 2);
-        const float w = (float)wgt<Q>(i);
-        const float cu = cx * M.ux + cy * M.uy + cz * M.uz;
-        const float cF = cx * F0 + cy * F1 + cz * F2;
-        const float deqp = w * (base + 4.5f * M.rho * cu * cu);
-        const float eqm = 3.f * w * M.rho * cu;
-        const float Sp = w * (9.f * cu * cF - 3.f * uF);
-        const float Sm = 3.f * w * cF;
-        const float dp = 0.5f * (d[i] + d[i + 1]);
-        const float dm = 0.5f * (d[i] - d[i + 1]);
-        const float A = -wp * (dp - deqp) + kp * Sp;
-        const float B = -wm * (dm - eqm) + km * Sm;
-        const float di = d[i], dj = d[i + 1];
-        d[i] = keep ? dj : di + A + B;
-        d[i + 1] = keep ? di : dj + A - B;
-    }
-}
-
-// Multiple-relaxation-time collision on deviations.  Forward transform
-// m = M d; every moment relaxes toward its equilibrium moment with the rate
-// of its group (viscous: wnu; ghosts: the domain's five rates) and takes the
-// Guo source moment with weight (1 - s/2); density is unchanged and the
-// momentum moments change by exactly F.  The equilibrium and source moments
-// are closed forms in rho, u, F with lattice constants fixed at compile
-// time.  Back with M^-1 = M^T diag(1/|row|^2).
-template <int Q>
-__device__ inline void mrt_collide(const LatticeArgs &a, float (&d)[Q], float drho, const Macro &M, float wnu,
-                                   bool keep = false)
-{
-    const float F[3] = {a.F[0], a.F[1], a.F[2]};
-    const float U[3] = {M.ux, M.uy, M.uz};
-    const float usq = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
-    const float uF = U[0] * F[0] + U[1] * F[1] + U[2] * F[2];
-    const float base = drho - 1.5f * M.rho * usq;
-    const float rate[8] = {0.f, 0.f, wnu, a.mrt[0], a.mrt[1], a.mrt[2], a.mrt[3], a.mrt[4]};
-    float m[Q];
-    for_dirs<0, Q>([&](auto R) {
-        constexpr int r = decltype(R)::value;
-        float acc = 0.f;
-        for_dirs<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            constexpr int mv = mrt_value<Q>(r, i);
-            if constexpr (mv == 1)
-                acc += d[i];
-            else if constexpr (mv == -1)
-                acc -= d[i];
-            else if constexpr (mv != 0)
-                acc += (float)mv * d[i];
-        });
-        m[r] = acc;
-    });
-    for_dirs<0, Q>([&](auto R) {
-        constexpr int r = decltype(R)::value;
-        constexpr int grp = mrt_group<Q>(r);
-        if constexpr (grp == MG_J) {
-            m[r] += keep ? 0.f : F[mrt_j_axis<Q>(r)];
-        } else if constexpr (grp != MG_RHO) {
-            constexpr float A = (float)mrt_A<Q>(r);
-            float meq = A * base, ms = -3.f * A * uF;
-            for_dirs<0, 3>([&](auto K) {
-                constexpr int k = decltype(K)::value;
-                constexpr float B = (float)mrt_B<Q>(r, k);
-                if constexpr (B != 0.f) {
-                    meq += 3.f * M.rho * B * U[k];
-                    ms += 3.f * B * F[k];
-                }
-                for_dirs<0, 3>([&](auto L) {
-                    constexpr int l = decltype(L)::value;
-                    constexpr float C = (float)mrt_C<Q>(r, k, l);
-                    if constexpr (C != 0.f) {
-                        meq += 4.5f * M.rho * C * U[k] * U[l];
-                        ms += 9.f * C * U[k] * F[l];
-                    }
-                });
-            });
-            const float sr = rate[grp];
-            const float dmr = -sr * (m[r] - meq) + (1.f - 0.5f * sr) * ms;
-            m[r] += keep ? 0.f : dmr;
-        }
-    });
-    for_dirs<0, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        float acc = 0.f;
-        for_dirs<0, Q>([&](auto R) {
-            constexpr int r = decltype(R)::value;
-            constexpr int mv = mrt_value<Q>(r, i);
-            if constexpr (mv != 0) acc += ((float)mv / (float)mrt_norm<Q>(r)) * m[r];
-        });
-        d[i] = acc;
-    });
-}
-
-// Value a cut link returns to its own cell (deviation form).  The face's
-// parameters are picked with an unrolled compare chain (uniform values,
-// per-lane selects) rather than by indexing the argument block with a
-// per-lane face number, which would force the block into scratch memory.
-template <int Q>
-__device__ inline float wall_value(const LatticeArgs &a, int face, int i, float v, const Macro &M)
-{
-    if (face < 0) return v;  // solid neighbour: plain bounce-back
-    int k = BC_NOSLIP;
-    float uw0 = 0.f, uw1 = 0.f, uw2 = 0.f, rw = 1.f;
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-        const bool sel = face == f;
-        k = sel ? a.bc[f] : k;
-        uw0 = sel ? a.ubc[f][0] : uw0;
-        uw1 = sel ? a.ubc[f][1] : uw1;
-        uw2 = sel ? a.ubc[f][2] : uw2;
-        rw = sel ? a.rhobc[f] : rw;
-    }
-    const float w = (float)wgt<Q>(i);
-    const int cx = cdir(i, 0), cy = cdir(i, 1), cz = cdir(i, 2);
-    if (k == BC_VELOCITY) return v - 6.f * w * rw * (cx * uw0 + cy * uw1 + cz * uw2);
-    if (k == BC_PRESSURE) {
-        const float cu = cx * M.ux + cy * M.uy + cz * M.uz;
-        const float usq = M.ux * M.ux + M.uy * M.uy + M.uz * M.uz;
-        return -v + 2.f * w * (rw - 1.f + rw * (4.5f * cu * cu - 1.5f * usq));
-    }
-    return v;
-}
-
-// One path for every cell: the odd step selects the cell's own slot for
-// links cut by a face or a solid neighbour (read side) and sends cut links'
-// values to the own slot (write side); velocity and pressure faces modify
-// those values in registers.
-template <int Q, int ST, bool MASK>
-__device__ inline void load_all(const LatticeArgs &a, const Geom &g, uint32_t m, int odd, float (&d)[Q])
-{
-    using S = Store<ST>;
-    const typename S::T *A = (const typename S::T *)a.pdf;
-    if (!odd) {
-        const typename S::T *R = A + pidx<Q>(a, 0, g.row, g.x);
-        for_dirs<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            d[i] = S::template ld<Hint<i>::even>(R + (uint64_t)i * (uint32_t)a.nx);
-        });
-    } else {
-        for_dirs<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
-            const bool cut = face_cut(g, -dx, -dy, -dz) || (MASK && ((m >> opp(i)) & 1u));
-            const uint64_t k = cut ? pidx<Q>(a, i, g.row, g.x) : pidx_nbr<Q>(a, g, opp(i), -dx, -dy, -dz);
-            d[i] = S::template ld<Hint<i>::odd>(A + k);
-        });
-    }
-}
-
-template <int Q, int ST, bool MASK, bool SWAP>
-__device__ inline void store_all(const LatticeArgs &a, const Geom &g, uint32_t m, int odd, const float (&d)[Q],
-                                 const Macro &M, bool keep)
-{
-    using S = Store<ST>;
-    typename S::T *A = (typename S::T *)a.pdf;
-    if (!odd) {
-        typename S::T *R = A + pidx<Q>(a, 0, g.row, g.x);
-        for_dirs<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
-            float v = d[i];
-            if (a.any_vp && !keep && face_cut(g, dx, dy, dz))
-                v = wall_value<Q>(a, deciding_face(a, g, dx, dy, dz), i, v, M);
-            // a kept (solid) lane puts every slot's own value back (the TRT
-            // collision has already exchanged its pairs)
-            if constexpr (MASK && SWAP) v = keep ? d[opp(i)] : v;
-            S::template st<Hint<i>::even>(R + (uint64_t)opp(i) * (uint32_t)a.nx, v);
-        });
-    } else {
-        for_dirs<0, Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
-            const bool fcut = face_cut(g, dx, dy, dz);
-            const bool cut = fcut || (MASK && ((m >> i) & 1u));
-            float v = d[i];
-            if (a.any_vp && fcut) v = wall_value<Q>(a, deciding_face(a, g, dx, dy, dz), i, v, M);
-            const uint64_t k = cut ? pidx<Q>(a, opp(i), g.row, g.x) : pidx_nbr<Q>(a, g, i, dx, dy, dz);
-            S::template st<Hint<i>::odd>(A + k, v);
-        });
-    }
-}
 
 // ---------------------------------------------------------------------------
 // the fused stream-collide kernel
@@ -768,7 +205,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_init_eq(LatticeArgs a, const
     for (int i = 0; i < Q; ++i) {
         const double cu = cdir(i, 0) * ux + cdir(i, 1) * uy + cdir(i, 2) * uz;
         const double dev = wgt<Q>(i) * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
-        A[pidx<Q>(a, i, g.row, g.x)] = S::cvt(solid ? 0.f : (float)dev);
+        A[index_t0<Q>(a, g, i)] = S::cvt(solid ? 0.f : (float)dev);
     }
 }
 
@@ -784,7 +221,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_set_pdfs(LatticeArgs a, cons
     typename S::T *A = (typename S::T *)a.pdf;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        A[pidx<Q>(a, i, g.row, g.x)] = S::cvt((float)(f[(uint64_t)i * a.n + g.c] - wgt<Q>(i)));
+        A[index_t0<Q>(a, g, i)] = S::cvt((float)(f[(uint64_t)i * a.n + g.c] - wgt<Q>(i)));
     }
 }
 
@@ -1004,25 +441,6 @@ static hipError_t step_q_st(const LatticeArgs &a, int cl, int coll, int odd, hip
         step_coll<Q, ST, COLL_TRT>(a, cl, mk, odd, L, s);
     }
     return hipGetLastError();
-}
-
-// Calls f(integral_constant<Q>, integral_constant<ST>) for the runtime pair.
-template <class Fn>
-static hipError_t dispatch(int q, int st, Fn &&f)
-{
-    using I19 = std::integral_constant<int, 19>;
-    using I27 = std::integral_constant<int, 27>;
-    using S0 = std::integral_constant<int, ST_F32>;
-    using S1 = std::integral_constant<int, ST_F16>;
-    using S2 = std::integral_constant<int, ST_BF16>;
-    if (q == 19) {
-        if (st == ST_F32) return f(I19{}, S0{});
-        if (st == ST_F16) return f(I19{}, S1{});
-        return f(I19{}, S2{});
-    }
-    if (st == ST_F32) return f(I27{}, S0{});
-    if (st == ST_F16) return f(I27{}, S1{});
-    return f(I27{}, S2{});
 }
 
 hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s)

@@ -21,6 +21,7 @@ BC = {"periodic": 0, "noslip": 1, "velocity": 2, "pressure": 3}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 CLOSURE = {"none": 0, "smagorinsky": 1, "mlp": 2}
 COLLISION = {"trt": 0, "mrt": 1}
+STREAMING = {"aa": 0, "et": 1}
 MRT_DEFAULT_RATES = (1.19, 1.4, 1.2, 1.4, 1.98)
 MLP_NPARAM, MLP_NNORM = 1313, 24
 
@@ -49,7 +50,7 @@ class Domain(ctypes.Structure):
         ("rho_bc", ctypes.c_double * 6),
         ("storage", ctypes.c_int32), ("closure", ctypes.c_int32), ("use_flags", ctypes.c_int32),
         ("magic", ctypes.c_double), ("cs_smag", ctypes.c_double),
-        ("collision", ctypes.c_int32), ("mrt_rates", ctypes.c_double * 5),
+        ("collision", ctypes.c_int32), ("mrt_rates", ctypes.c_double * 5), ("streaming", ctypes.c_int32),
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
     ]
@@ -127,7 +128,8 @@ def _dev(t, dtype, device):
 
 
 def make_domain(shape, bc=("periodic",) * 6, u_bc=None, rho_bc=None, storage="f32", closure="none",
-                use_flags=False, magic=3.0 / 16.0, cs=0.1, collision="trt", mrt_rates=None) -> Domain:
+                use_flags=False, magic=3.0 / 16.0, cs=0.1, collision="trt", mrt_rates=None,
+                streaming="aa") -> Domain:
     d = Domain()
     lib().lbm_domain_defaults(ctypes.byref(d))
     d.nx, d.ny, d.nz = (int(v) for v in shape)
@@ -147,6 +149,7 @@ def make_domain(shape, bc=("periodic",) * 6, u_bc=None, rho_bc=None, storage="f3
     if mrt_rates is not None:
         for k in range(5):
             d.mrt_rates[k] = float(mrt_rates[k])
+    d.streaming = STREAMING[streaming] if isinstance(streaming, str) else int(streaming)
     return d
 
 
@@ -161,14 +164,14 @@ class Lattice:
 
     def __init__(self, shape, q: int = 19, tau: float = 0.6, force=(0.0, 0.0, 0.0), bc=("periodic",) * 6,
                  u_bc=None, rho_bc=None, solid: Optional[np.ndarray] = None, storage="f32", closure="none",
-                 magic=3.0 / 16.0, cs=0.1, collision="trt", mrt_rates=None, device="cuda:0"):
+                 magic=3.0 / 16.0, cs=0.1, collision="trt", mrt_rates=None, streaming="aa", device="cuda:0"):
         torch = _torch()
         self.device = torch.device(device)
         self.q = int(q)
         self.shape = tuple(int(v) for v in shape)
         self.n = self.shape[0] * self.shape[1] * self.shape[2]
         self.domain = make_domain(shape, bc, u_bc, rho_bc, storage, closure, solid is not None, magic, cs,
-                                  collision, mrt_rates)
+                                  collision, mrt_rates, streaming)
         nbytes = workspace_bytes(self.domain, self.q)
         # torch's caching allocator returns 512-byte aligned blocks
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)

@@ -37,6 +37,16 @@ def test_domain_defaults(L):
     d = lbm.make_domain((8, 4, 2))
     assert list(d.bc) == [0] * 6 and list(d.rho_bc) == [1.0] * 6
     assert d.magic == 3 / 16 and d.cs_smag == 0.1 and d.storage == 0 and d.closure == 0
+    assert d.collision == 0 and d.streaming == 0
+
+
+def test_rows_are_padded_to_whole_lines(L):
+    """Every direction segment starts on a 128-byte line: a 100-cell row
+    takes 128 FP32 cells (or 128 16-bit cells)."""
+    d32 = lbm.workspace_bytes(lbm.make_domain((100, 8, 4), storage="f32"), 19)
+    d16 = lbm.workspace_bytes(lbm.make_domain((100, 8, 4), storage="f16"), 19)
+    assert 19 * 4 * 128 * 32 <= d32 and 19 * 2 * 128 * 32 <= d16
+    assert d32 - d16 == 19 * 2 * 128 * 32
 
 
 def test_workspace_bytes_scales_with_storage(L):
@@ -61,6 +71,26 @@ def test_workspace_bytes_rejects(L, kw, q):
     assert L.lbm_last_error(None)
 
 
+def test_et_workspace_holds_the_ghost_layers(L):
+    """Esoteric Twist: one more cell along each non-periodic axis (the ghost
+    layer beyond its + face); nothing extra for periodic axes."""
+    nx, ny, nz = 64, 32, 16
+    walls = ("velocity", "pressure", "noslip", "noslip", "periodic", "periodic")
+    aa = lbm.workspace_bytes(lbm.make_domain((nx, ny, nz), bc=walls), 19)
+    et = lbm.workspace_bytes(lbm.make_domain((nx, ny, nz), bc=walls, streaming="et"), 19)
+    # rows are padded to whole 128-byte lines: 65 cells -> 96 in FP32
+    extra = 19 * 4 * (96 * (ny + 1) * nz - nx * ny * nz)
+    assert extra <= et - aa < extra + 256
+    per = lbm.make_domain((nx, ny, nz))
+    assert lbm.workspace_bytes(per, 19) == lbm.workspace_bytes(lbm.make_domain((nx, ny, nz), streaming="et"), 19)
+    assert d_rejects(L, lbm.make_domain((8, 8, 8), streaming=5))
+
+
+def d_rejects(L, d):
+    out = ctypes.c_size_t(0)
+    return L.lbm_workspace_bytes(ctypes.byref(d), 19, ctypes.byref(out)) == lbm.LBM_EINVAL
+
+
 def test_too_many_cells_is_enomem(L):
     d = lbm.make_domain((2048, 1024, 1024))
     out = ctypes.c_size_t(0)
@@ -74,7 +104,7 @@ def _create(L, d, q=19, tau=0.6, flags=None):
     return rc, h
 
 
-@pytest.mark.parametrize("case", ["tau", "pairing", "bcenum", "null_ws", "small_ws", "align", "flags"])
+@pytest.mark.parametrize("case", ["tau", "pairing", "bcenum", "null_ws", "small_ws", "align", "flags", "et_mlp"])
 def test_create_rejects_before_device(L, case):
     d = lbm.make_domain((8, 8, 8))
     need = lbm.workspace_bytes(d, 19)
@@ -97,6 +127,10 @@ def test_create_rejects_before_device(L, case):
     elif case == "flags":
         buf = (ctypes.c_uint8 * 512)()
         flags = ctypes.cast(buf, ctypes.c_void_p)
+    elif case == "et_mlp":
+        d.streaming = lbm.STREAMING["et"]
+        d.closure = lbm.CLOSURE["mlp"]
+        d.workspace_bytes = lbm.workspace_bytes(d, 19)
     rc, h = _create(L, d, tau=tau, flags=flags)
     assert rc == lbm.LBM_EINVAL and not h.value
     assert len(L.lbm_last_error(None)) > 0

@@ -1,0 +1,82 @@
+"""Esoteric Twist streaming on the GPU beyond the oracle parity cases of
+test_gpu_parity.py (which run every scheme): the two in-place schemes give
+the same populations, in every storage format, and the learned closure is
+refused with the Esoteric Twist."""
+import numpy as np
+import pytest
+
+from paper_2305_09910_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_09910_amd import lbm
+    lbm.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_et_agrees_with_aa(q, storage):
+    """Same collision on the same values: AA and the Esoteric Twist differ
+    only by the FP32 rounding order the compiler picks in each kernel, with
+    solids, velocity / pressure / no-slip faces (ghost layers on x and y) and
+    a force, after odd and even step counts.
+
+    Bound after n steps: each step may round each value differently by a few
+    ulps of its storage format, and the differences stay at most linear in n
+    for a stable run.  FP32: n * 4 * 2^-24 * max|f|; 16-bit: n * 2 * ulp of
+    the largest stored deviation (2^-10 and 2^-7 relative for FP16 / BF16)."""
+    from paper_2305_09910_amd import lbm
+    shape = (40, 18, 12)
+    solid = np.zeros(shape[::-1], np.uint8)
+    solid[3:7, 5:9, 10:15] = 1
+    solid[:, 0, 20] = 1
+    uw = np.zeros((6, 3))
+    uw[0] = (0.03, 0.002, 0.0)
+    kw = dict(q=q, tau=0.58, force=(1e-5, 0, -2e-6), bc=("velocity", "pressure", "noslip", "noslip", "periodic",
+                                                          "periodic"), u_bc=uw, solid=solid, storage=storage)
+    print(f"[case] q={q} storage={storage}", flush=True)
+    a = lbm.Lattice(shape, streaming="aa", **kw)
+    e = lbm.Lattice(shape, streaming="et", **kw)
+    rho, u = inputs.uniform_flow(*shape, (0.03, 0.0, 0.0))
+    u += inputs.perturbation(u.shape, 0.005, seed=q)
+    u[:, solid == 1] = 0.0
+    a.init_equilibrium(rho, u)
+    e.init_equilibrium(rho, u)
+    fluid = torch.as_tensor(solid == 0, device=a.device)
+    w = torch.as_tensor(lbm_weights(q), device=a.device, dtype=torch.float64)[:, None, None, None]
+    for n in (1, 50, 51):
+        a.step(n - a.time)
+        e.step(n - e.time)
+        fa, fe = a.get_pdfs(), e.get_pdfs()
+        diff = float((fa - fe)[:, fluid].abs().max())
+        if storage == "f32":
+            bound = n * 4 * 2.0 ** -24 * float(fa[:, fluid].abs().max())
+        else:
+            dmax = float((fa - w)[:, fluid].abs().max())
+            rel = 2.0 ** -10 if storage == "f16" else 2.0 ** -7
+            bound = n * 2 * rel * 2.0 ** np.floor(np.log2(dmax))
+        print(f"n={n}: max |f_aa - f_et| = {diff:.3e} (bound {bound:.3e})")
+        assert diff <= bound, (n, diff, bound)
+    ma, pa = a.totals()
+    me, pe = e.totals()
+    assert abs(ma - me) <= 1e-6 * ma and np.abs(pa - pe).max() <= 1e-6 * ma
+
+
+def lbm_weights(q):
+    import oracle
+    return oracle.velocity_set(q)[1]
+
+
+def test_et_refuses_the_learned_closure():
+    from paper_2305_09910_amd import lbm
+    with pytest.raises(lbm.LBMError) as exc:
+        lbm.Lattice((16, 8, 8), closure="mlp", streaming="et")
+    assert exc.value.code == lbm.LBM_EINVAL

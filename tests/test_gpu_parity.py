@@ -40,13 +40,13 @@ BCS = {"periodic": oracle.BC_PERIODIC, "noslip": oracle.BC_NOSLIP, "velocity": o
 
 
 def pair(shape, q=19, tau=0.6, force=(0, 0, 0), bc=("periodic",) * 6, u_bc=None, rho_bc=None, solid=None,
-         storage="f32", closure="none", cs=0.1, magic=3 / 16, collision="trt", mrt_rates=None):
+         storage="f32", closure="none", cs=0.1, magic=3 / 16, collision="trt", mrt_rates=None, streaming="aa"):
     """A GPU lattice and an oracle simulation with identical parameters."""
-    print(f"[case] q={q} shape={shape} bc={bc} storage={storage} closure={closure} collision={collision}",
-          flush=True)
+    print(f"[case] q={q} shape={shape} bc={bc} storage={storage} closure={closure} collision={collision} "
+          f"streaming={streaming}", flush=True)
     g = _lbm().Lattice(shape, q=q, tau=tau, force=force, bc=bc, u_bc=u_bc, rho_bc=rho_bc, solid=solid,
                        storage=storage, closure=closure, cs=cs, magic=magic, collision=collision,
-                       mrt_rates=mrt_rates)
+                       mrt_rates=mrt_rates, streaming=streaming)
     cl = {"none": oracle.CL_NONE, "smagorinsky": oracle.CL_SMAG, "mlp": oracle.CL_MLP}[closure]
     o = oracle.Sim(q, shape, bc=tuple(BCS[b] for b in bc), tau=tau, magic=magic, force=force, u_bc=u_bc,
                    rho_bc=rho_bc, solid=solid, closure=cl, cs=cs)
@@ -67,10 +67,11 @@ def max_rel(g_pdfs, o_pdfs, solid=None):
 # ---------------------------------------------------------------------------
 # FP32 parity
 # ---------------------------------------------------------------------------
-def test_taylor_green_32cubed_1000_steps():
+@pytest.mark.parametrize("streaming", ["aa", "et"])
+def test_taylor_green_32cubed_1000_steps(streaming):
     """Taylor-Green vortex, D3Q19 TRT, 32^3 periodic, nu = 0.01, u0 = 0.05."""
     n = 32
-    g, o = pair((n, n, n), tau=3 * 0.01 + 0.5)
+    g, o = pair((n, n, n), tau=3 * 0.01 + 0.5, streaming=streaming)
     rho, u = inputs.taylor_green(n, n, n, 0.05)
     g.init_equilibrium(rho, u)
     o.init_equilibrium(rho, u)
@@ -97,16 +98,18 @@ def test_taylor_green_32cubed_1000_steps():
     assert abs(amp / expect - 1) < 0.01
 
 
+@pytest.mark.parametrize("streaming", ["aa", "et"])
 @pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("nsteps", [1, 2, 3, 10, 11])
-def test_parity_aware_state_after_odd_and_even_steps(q, nsteps):
+def test_parity_aware_state_after_odd_and_even_steps(q, nsteps, streaming):
     shape = (16, 12, 8)
     solid = np.zeros(shape[::-1], np.uint8)
     solid[3:5, 4:7, 5:9] = 1
     uw = np.zeros((6, 3))
     uw[0] = (0.03, 0.004, -0.002)
     g, o = pair(shape, q=q, tau=0.57, force=(2e-5, -1e-5, 3e-6),
-                bc=("velocity", "pressure", "noslip", "noslip", "periodic", "periodic"), u_bc=uw, solid=solid)
+                bc=("velocity", "pressure", "noslip", "noslip", "periodic", "periodic"), u_bc=uw, solid=solid,
+                streaming=streaming)
     rng = np.random.default_rng(nsteps)
     rho = 1 + rng.uniform(-0.01, 0.01, shape[::-1])
     u = rng.uniform(-0.03, 0.03, (3,) + shape[::-1])
@@ -124,8 +127,9 @@ def test_parity_aware_state_after_odd_and_even_steps(q, nsteps):
     assert np.array_equal(gat, full)
 
 
+@pytest.mark.parametrize("streaming", ["aa", "et"])
 @pytest.mark.parametrize("q", [19, 27])
-def test_every_boundary_kind_on_every_axis(q):
+def test_every_boundary_kind_on_every_axis(q, streaming):
     """No-slip, velocity and pressure faces on all three axes with solids and
     a force, 300 steps."""
     shape = (20, 14, 10)
@@ -138,7 +142,8 @@ def test_every_boundary_kind_on_every_axis(q):
     uw[4] = (0.0, 0.005, 0.01)
     rb = np.array([1.0, 1.002, 1.0, 1.0, 1.0, 0.999])
     bc = ("velocity", "pressure", "noslip", "velocity", "velocity", "pressure")
-    g, o = pair(shape, q=q, tau=0.8, force=(1e-5, 2e-6, -3e-6), bc=bc, u_bc=uw, rho_bc=rb, solid=solid)
+    g, o = pair(shape, q=q, tau=0.8, force=(1e-5, 2e-6, -3e-6), bc=bc, u_bc=uw, rho_bc=rb, solid=solid,
+                streaming=streaming)
     rho, u = inputs.uniform_flow(*shape, (0.01, 0.0, 0.0))
     g.init_equilibrium(rho, u)
     o.init_equilibrium(rho, u)
@@ -149,13 +154,14 @@ def test_every_boundary_kind_on_every_axis(q):
     assert err <= TOL32
 
 
-def test_channel_1000_steps():
+@pytest.mark.parametrize("streaming", ["aa", "et"])
+def test_channel_1000_steps(streaming):
     """Channel shape (walls on y, periodic x and z, force in x, parabola plus
     5% noise), a 64x32x32 copy of the 256x128x128 channel, 1000 steps."""
     nx, ny, nz = 64, 32, 32
     F = 8 * (1 / 300) * 0.05 / ny ** 2
     g, o = pair((nx, ny, nz), tau=0.51, force=(F, 0, 0), bc=("periodic", "periodic", "noslip", "noslip",
-                                                             "periodic", "periodic"))
+                                                             "periodic", "periodic"), streaming=streaming)
     rho, u = inputs.channel(nx, ny, nz, 0.05, 0.05, seed=1234)
     g.init_equilibrium(rho, u)
     o.init_equilibrium(rho, u)
@@ -170,7 +176,8 @@ def test_channel_1000_steps():
     assert abs(mg - mo) / mo < 1e-7
 
 
-def test_obstacle_d3q27_200_steps():
+@pytest.mark.parametrize("streaming", ["aa", "et"])
+def test_obstacle_d3q27_200_steps(streaming):
     """D3Q27 obstacle flow: velocity inflow 0.04 at -x, pressure outflow at
     +x, periodic y/z, random spheres (10% solid, radii 4-10), 96x64x64, 200 steps."""
     shape = (96, 64, 64)
@@ -178,7 +185,7 @@ def test_obstacle_d3q27_200_steps():
     uw = np.zeros((6, 3))
     uw[0] = (0.04, 0, 0)
     g, o = pair(shape, q=27, tau=0.56, bc=("velocity", "pressure", "periodic", "periodic", "periodic",
-                                            "periodic"), u_bc=uw, solid=solid)
+                                            "periodic"), u_bc=uw, solid=solid, streaming=streaming)
     rho, u = inputs.uniform_flow(*shape, (0.04, 0, 0))
     u[:, solid == 1] = 0.0
     g.init_equilibrium(rho, u)
@@ -190,11 +197,12 @@ def test_obstacle_d3q27_200_steps():
     assert err <= TOL32
 
 
+@pytest.mark.parametrize("streaming", ["aa", "et"])
 @pytest.mark.parametrize("q", [19, 27])
-def test_smagorinsky_closure(q):
+def test_smagorinsky_closure(q, streaming):
     nx, ny, nz = 32, 16, 16
     g, o = pair((nx, ny, nz), q=q, tau=0.505, force=(2e-6, 0, 0), closure="smagorinsky", cs=0.1,
-                bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"))
+                bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"), streaming=streaming)
     rho, u = inputs.channel(nx, ny, nz, 0.08, 0.2, seed=3)
     g.init_equilibrium(rho, u)
     o.init_equilibrium(rho, u)
@@ -226,8 +234,9 @@ def test_mrt_channel(q, closure):
     assert err <= TOL32
 
 
+@pytest.mark.parametrize("streaming", ["aa", "et"])
 @pytest.mark.parametrize("q", [19, 27])
-def test_mrt_every_boundary_kind_and_solids(q):
+def test_mrt_every_boundary_kind_and_solids(q, streaming):
     shape = (20, 14, 10)
     solid = np.zeros(shape[::-1], np.uint8)
     solid[4:6, 6:9, 8:12] = 1
@@ -236,7 +245,7 @@ def test_mrt_every_boundary_kind_and_solids(q):
     uw[3] = (0.01, -0.002, 0.0)
     bc = ("velocity", "pressure", "noslip", "velocity", "periodic", "periodic")
     g, o = pair(shape, q=q, tau=0.7, force=(1e-5, 2e-6, -3e-6), bc=bc, u_bc=uw, solid=solid, collision="mrt",
-                mrt_rates=(1.1, 1.3, 1.25, 1.5, 1.7))
+                mrt_rates=(1.1, 1.3, 1.25, 1.5, 1.7), streaming=streaming)
     rho, u = inputs.uniform_flow(*shape, (0.01, 0.0, 0.0))
     g.init_equilibrium(rho, u)
     o.init_equilibrium(rho, u)
@@ -260,9 +269,11 @@ def test_mrt_rejects_mlp_and_bad_rates():
 # ---------------------------------------------------------------------------
 # state readers and robustness
 # ---------------------------------------------------------------------------
-def test_moments_and_set_pdfs_roundtrip():
+@pytest.mark.parametrize("streaming", ["aa", "et"])
+def test_moments_and_set_pdfs_roundtrip(streaming):
     shape = (24, 10, 6)
-    g, o = pair(shape, force=(1e-4, 0, 0), bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"))
+    g, o = pair(shape, force=(1e-4, 0, 0), bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"),
+                streaming=streaming)
     c, w, _ = oracle.velocity_set(19)
     W = w[:, None, None, None]
     f = W * (1.0 + inputs.perturbation((19,) + shape[::-1], 0.05, seed=1))
@@ -300,9 +311,11 @@ def test_low_precision_storage_rounding(storage, tdtype):
     assert np.allclose(got, expect, rtol=0, atol=1e-17)
 
 
-def test_run_twice_bit_identical_and_checkpoint_resume():
+@pytest.mark.parametrize("streaming", ["aa", "et"])
+def test_run_twice_bit_identical_and_checkpoint_resume(streaming):
     shape = (32, 16, 8)
-    kw = dict(tau=0.55, force=(1e-5, 0, 0), bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"))
+    kw = dict(tau=0.55, force=(1e-5, 0, 0), bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"),
+              streaming=streaming)
     lbm = _lbm()
     rho, u = inputs.channel(*shape, 0.05, 0.05, seed=7)
     a = lbm.Lattice(shape, **kw)
