@@ -408,19 +408,25 @@ hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, 
     return hipGetLastError();
 }
 
+template <int Q, int ST, int CL, bool MASK, int COLL>
+static void launch_sc(const LatticeArgs &a, int odd, const Launch &L, hipStream_t s)
+{
+    k_stream_collide<Q, ST, CL, MASK, COLL><<<L.grid, L.block, 0, s>>>(a, odd);
+}
+
 template <int Q, int ST, int COLL>
 static void step_coll(const LatticeArgs &a, int cl, bool mk, int odd, const Launch &L, hipStream_t s)
 {
     if (cl == CL_NONE) {
         if (mk)
-            k_stream_collide<Q, ST, CL_NONE, true, COLL><<<L.grid, L.block, 0, s>>>(a, odd);
+            launch_sc<Q, ST, CL_NONE, true, COLL>(a, odd, L, s);
         else
-            k_stream_collide<Q, ST, CL_NONE, false, COLL><<<L.grid, L.block, 0, s>>>(a, odd);
+            launch_sc<Q, ST, CL_NONE, false, COLL>(a, odd, L, s);
     } else {
         if (mk)
-            k_stream_collide<Q, ST, CL_SMAG, true, COLL><<<L.grid, L.block, 0, s>>>(a, odd);
+            launch_sc<Q, ST, CL_SMAG, true, COLL>(a, odd, L, s);
         else
-            k_stream_collide<Q, ST, CL_SMAG, false, COLL><<<L.grid, L.block, 0, s>>>(a, odd);
+            launch_sc<Q, ST, CL_SMAG, false, COLL>(a, odd, L, s);
     }
 }
 
@@ -432,9 +438,9 @@ static hipError_t step_q_st(const LatticeArgs &a, int cl, int coll, int odd, hip
     if (cl == CL_MLP) {  // the learned closure runs with the TRT collision
         if (coll != COLL_TRT) return hipErrorInvalidValue;
         if (mk)
-            k_stream_collide<Q, ST, CL_MLP, true, COLL_TRT><<<L.grid, L.block, 0, s>>>(a, odd);
+            launch_sc<Q, ST, CL_MLP, true, COLL_TRT>(a, odd, L, s);
         else
-            k_stream_collide<Q, ST, CL_MLP, false, COLL_TRT><<<L.grid, L.block, 0, s>>>(a, odd);
+            launch_sc<Q, ST, CL_MLP, false, COLL_TRT>(a, odd, L, s);
     } else if (coll == COLL_MRT) {
         step_coll<Q, ST, COLL_MRT>(a, cl, mk, odd, L, s);
     } else {
