@@ -68,7 +68,8 @@ def demo_closure_weights(seed=9):
     return np.concatenate([p, norm]).astype(np.float32)
 
 
-KERNEL_SOURCES = ["paper_2305_09910_amd/csrc/lbm_kernels.hip", "paper_2305_09910_amd/csrc/lattice.h",
+KERNEL_SOURCES = ["paper_2305_09910_amd/csrc/lbm_kernels.hip", "paper_2305_09910_amd/csrc/lbm_et.hip",
+                  "paper_2305_09910_amd/csrc/lattice.h",
                   "paper_2305_09910_amd/csrc/stencil.h", "paper_2305_09910_amd/csrc/internal.h",
                   "paper_2305_09910_amd/csrc/mlp_wave.h"]
 PROFILE = "profiles/stream_collide_channel_256x128x128.md"

@@ -33,3 +33,25 @@ def test_closure_study_small():
     post = res["a_posteriori"]
     for name in ("smagorinsky", "mlp"):
         assert post[name]["finite"] and math.isfinite(post[name]["l2_velocity_error"])
+
+
+def test_closure_gain_a_posteriori_vortical_channel():
+    """With a vortical start (band-limited solenoidal perturbation, rms 0.02,
+    peak wavelength 16 fine cells) the filtered fine flow has a resolved
+    subgrid stress.  Coarse 64x32x32 against the filtered 256x128x128 run,
+    100 coarse steps: the trained network predicts the correction better
+    than Smagorinsky and zero on a held-out snapshot, and its coarse run is
+    closer to the filtered fine run than the run without a model.  Measured
+    over three seeds: 2.8-3.1% below no model, within 0.3% of Smagorinsky;
+    the bounds leave margin."""
+    from paper_2305_09910_amd import closure
+    cfg = closure.ClosureConfig(coarse=(64, 32, 32), factor=4, tau_c=0.503, noise=0.05, vortical_rms=0.02,
+                                vortical_wavelength=16, seed=1234, spinup=400, snapshots=3, every=200,
+                                train_steps=400, batch=16384, lr=2e-3, eval_coarse_steps=100)
+    res, _ = closure.study(cfg, log=print)
+    ap = res["a_priori_heldout"]
+    post = {k: v["l2_velocity_error"] for k, v in res["a_posteriori"].items()}
+    print(ap, post)
+    assert ap["mse_mlp"] < ap["mse_smagorinsky"] < ap["mse_zero"]
+    assert post["mlp"] < 0.99 * post["none"]
+    assert abs(post["mlp"] / post["smagorinsky"] - 1) < 0.02
