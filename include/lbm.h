@@ -183,7 +183,10 @@ int lbm_moments(lbm_ctx *ctx, float *rho_dev, float *u_dev);
  * LBM_ENONFINITE if any fluid population is NaN or Inf. */
 int lbm_totals(lbm_ctx *ctx, double *mass, double mom[3]);
 
-/* Bytes of the raw population state (for checkpoints). */
+/* Bytes of the raw population store (for checkpoints): q rows of sx cells
+ * per stored row, sx = nx rounded up to whole 128-byte lines, with the
+ * Esoteric Twist's ghost layers included.  Its layout is internal; only
+ * lbm_load_state of a context with the same domain reads it back. */
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *out);
 
 /* Copy the raw state to dst_dev (lbm_state_bytes bytes) and report the
