@@ -293,6 +293,39 @@ def test_inflow_outflow_plug_flow(q):
     assert np.abs(r - 1).max() < 1e-6
 
 
+def duct_with_sphere(nx=32, ny=16, nz=16):
+    """A duct (velocity inlet 0.04 at -x, pressure outlet at +x, periodic y
+    and z) with one solid sphere of radius sqrt(12) off the axes."""
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    solid = ((xx - 13) ** 2 + (yy - 7.5) ** 2 + (zz - 8.2) ** 2 <= 12).astype(np.uint8)
+    uw = np.zeros((6, 3))
+    uw[0] = (0.04, 0, 0)
+    return solid, uw
+
+
+def plane_fluxes(rho, u, solid):
+    """Mass flux sum_{y,z} rho u_x through every x plane."""
+    return (rho * u[0] * (solid == 0)).sum(axis=(0, 1))
+
+
+def test_obstacle_flow_steady_mass_flux():
+    """Past an obstacle at steady state, continuity makes the mass flux
+    through every x plane the same, and equal to what the inlet supplies
+    (rho ~ 1 times 0.04 times the face area).  D3Q27, 4000 steps (about 20
+    acoustic crossings); the oracle reaches 3.4e-5 relative spread."""
+    nx, ny, nz = 32, 16, 16
+    solid, uw = duct_with_sphere(nx, ny, nz)
+    sim = oracle.Sim(27, (nx, ny, nz), bc=(BC_VELOCITY, BC_PRESSURE, 0, 0, 0, 0), tau=0.56, u_bc=uw, solid=solid)
+    rho, u = inputs.uniform_flow(nx, ny, nz, (0.04, 0, 0))
+    u[:, solid == 1] = 0.0
+    sim.init_equilibrium(rho, u)
+    sim.step(4000)
+    r, uu = sim.moments()
+    flux = plane_fluxes(r, uu, solid)
+    assert np.abs(flux / flux.mean() - 1).max() < 1e-3
+    assert abs(flux[0] / (0.04 * ny * nz) - 1) < 1e-2
+
+
 def test_solid_rows_equal_wall_faces():
     """A channel walled by solid rows equals the same channel walled by no-slip faces."""
     nx, ny, nz = 6, 10, 4
