@@ -198,6 +198,35 @@ def test_obstacle_d3q27_200_steps(streaming):
 
 
 @pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("shape,walls", [
+    ((1, 9, 7), ("periodic", "periodic", "noslip", "noslip", "velocity", "pressure")),  # one cell along periodic x
+    ((11, 1, 6), ("pressure", "velocity", "noslip", "noslip", "periodic", "periodic")),  # one cell between two walls
+    ((7, 5, 1), ("noslip", "velocity", "periodic", "periodic", "periodic", "periodic")),  # 2-D slab
+    ((70, 3, 2), ("velocity", "pressure", "periodic", "periodic", "noslip", "noslip")),  # ragged row (64 + 6)
+    ((1, 1, 1), ("periodic",) * 6),                                                      # a single cell
+])
+@pytest.mark.parametrize("q", [19, 27])
+def test_degenerate_and_ragged_shapes(q, shape, walls, streaming):
+    """Axes one cell thick (a periodic axis wrapping onto the cell itself, a
+    layer between two walls), a 2-D slab, a row that ends in a partial
+    wavefront, and a single cell: 25 steps with a force and moving walls."""
+    uw = np.zeros((6, 3))
+    uw[1] = (0.0, 0.01, -0.005)
+    uw[3] = (0.004, 0.0, 0.0)
+    uw[4] = (0.01, 0.0, 0.0)
+    g, o = pair(shape, q=q, tau=0.66, force=(3e-5, -1e-5, 2e-5), bc=walls, u_bc=uw, streaming=streaming)
+    rng = np.random.default_rng(sum(shape))
+    rho = 1 + rng.uniform(-0.01, 0.01, shape[::-1])
+    u = rng.uniform(-0.02, 0.02, (3,) + shape[::-1])
+    g.init_equilibrium(rho, u)
+    o.init_equilibrium(rho, u)
+    for n in (1, 24):
+        g.step(n)
+        o.step(n)
+        assert max_rel(g.get_pdfs(), o.get_pdfs()) <= 1e-6, n
+
+
+@pytest.mark.parametrize("streaming", ["aa", "et"])
 def test_obstacle_flow_steady_mass_flux(streaming):
     """Duct past a sphere (velocity inlet, pressure outlet), D3Q27, 4000
     steps: the GPU state matches the oracle, and at steady state the mass
