@@ -76,10 +76,16 @@ PROFILE = "profiles/stream_collide_channel_256x128x128.md"
 
 
 def kernel_source_hash():
+    """Hash of the step kernels' code: comments and whitespace are dropped,
+    so that editing a comment does not invalidate a profile."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        src = open(os.path.join(ROOT, f)).read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

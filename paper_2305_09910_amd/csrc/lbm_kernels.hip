@@ -378,9 +378,10 @@ __global__ void __launch_bounds__(256) k_copy(const f32x4 *__restrict__ src, f32
 // ---------------------------------------------------------------------------
 Launch lattice_launch(const LatticeArgs &a)
 {
-    // LBM_BLOCK threads: BX cells along x (a row segment) times BY rows.
-    // Whole rows per block keep the +-1 shifted reads of the odd step inside
-    // one workgroup (no cache line shared between blocks within a row).
+    // LBM_BLOCK threads: BX cells along x (a row segment) times BY rows,
+    // BX the largest power of two up to LBM_BLOCK that divides nx.  When a
+    // row fits one workgroup, the +-1 shifted accesses of the odd step stay
+    // in it; wider rows share a line at each seam between workgroups.
     int bx = LBM_BLOCK;
     if (LBM_ROW_MAX > 0 && a.nx <= LBM_ROW_MAX && a.nx % 64 == 0) {
         Launch L;
