@@ -6,8 +6,10 @@
  * What it computes follows the paper's statement of the method (Section 2,
  * "The Lattice Boltzmann Method", Eq. (1) collision and Eq. (2) streaming),
  * with the collision operator read as a two-relaxation-time (TRT) operator
- * (the paper's D3Q19 "Double Relaxation Time" scheme of the LaBS section),
- * Guo body forcing, halfway bounce-back walls and periodic faces.  The memory
+ * (the paper's D3Q19 "Double Relaxation Time" scheme of the LaBS section) or
+ * as a multiple-relaxation-time operator in a moment space (the LAGOON
+ * collision, Section 5.2), Guo body forcing, halfway bounce-back walls,
+ * velocity and pressure faces, solid cells and periodic faces.  The memory
  * layout is deliberately different from the GPU path: two full lattices and a
  * push (scatter) streaming step, one loop nest per time step, no fusion
  * beyond what Eq. (1)-(2) state.
