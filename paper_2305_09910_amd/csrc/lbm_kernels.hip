@@ -389,6 +389,12 @@ Launch lattice_launch(const LatticeArgs &a)
         L.grid = dim3(1, a.ny, a.nz);
         return L;
     }
+    if (LBM_WIDE > 0 && a.nx % LBM_WIDE == 0) {
+        Launch L;
+        L.block = dim3(LBM_WIDE, 1, 1);
+        L.grid = dim3(a.nx / LBM_WIDE, a.ny, a.nz);
+        return L;
+    }
     while (bx > 32 && a.nx % bx != 0) bx >>= 1;
     if (a.nx % bx != 0) bx = 64;  // ragged rows: masked tail
     if (bx > a.nx) bx = a.nx <= 32 ? 32 : 64;

@@ -203,13 +203,15 @@ def test_obstacle_d3q27_200_steps(streaming):
     ((11, 1, 6), ("pressure", "velocity", "noslip", "noslip", "periodic", "periodic")),  # one cell between two walls
     ((7, 5, 1), ("noslip", "velocity", "periodic", "periodic", "periodic", "periodic")),  # 2-D slab
     ((70, 3, 2), ("velocity", "pressure", "periodic", "periodic", "noslip", "noslip")),  # ragged row (64 + 6)
+    ((512, 3, 2), ("velocity", "pressure", "noslip", "noslip", "periodic", "periodic")),  # 512-cell row segments
     ((1, 1, 1), ("periodic",) * 6),                                                      # a single cell
 ])
 @pytest.mark.parametrize("q", [19, 27])
 def test_degenerate_and_ragged_shapes(q, shape, walls, streaming):
     """Axes one cell thick (a periodic axis wrapping onto the cell itself, a
     layer between two walls), a 2-D slab, a row that ends in a partial
-    wavefront, and a single cell: 25 steps with a force and moving walls."""
+    wavefront, rows in 512-cell workgroups, and a single cell: 25 steps with
+    a force and moving walls."""
     uw = np.zeros((6, 3))
     uw[1] = (0.0, 0.01, -0.005)
     uw[3] = (0.004, 0.0, 0.0)
