@@ -178,10 +178,11 @@ def test_channel_1000_steps(streaming):
 
 @pytest.mark.parametrize("streaming", ["aa", "et"])
 def test_obstacle_d3q27_200_steps(streaming):
-    """D3Q27 obstacle flow: velocity inflow 0.04 at -x, pressure outflow at
-    +x, periodic y/z, random spheres (10% solid, radii 4-10), 96x64x64, 200 steps."""
-    shape = (96, 64, 64)
-    solid, _ = inputs.spheres(*shape, fill=0.10, rmin=4, rmax=10, x_margin=8, seed=2024)
+    """D3Q27 obstacle flow, the 128^3 copy of the 384^3 workload: velocity
+    inflow 0.04 at -x, pressure outflow at +x, periodic y/z, random spheres
+    filling 10% (radii 6-20, x margins scaled to 11 cells), 200 steps."""
+    shape = (128, 128, 128)
+    solid, _ = inputs.spheres(*shape, fill=0.10, rmin=6, rmax=20, x_margin=11, seed=2024)
     uw = np.zeros((6, 3))
     uw[0] = (0.04, 0, 0)
     g, o = pair(shape, q=27, tau=0.56, bc=("velocity", "pressure", "periodic", "periodic", "periodic",
