@@ -41,7 +41,23 @@ def build() -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    _build_example()
     return LIB
+
+
+EXAMPLE_SRC = os.path.join(HERE, "examples", "abi_tgv.cpp")
+EXAMPLE_BIN = os.path.join(HERE, "examples", "abi_tgv")
+
+
+def _build_example():
+    """The C ABI driven from plain host code (examples/abi_tgv.cpp), linked
+    against the library next to it."""
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17", EXAMPLE_SRC, "-o", EXAMPLE_BIN + ".tmp",
+           "-L" + HERE, "-llbm", "-Wl,-rpath,$ORIGIN/.."]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"example build failed:\n{r.stderr}")
+    os.replace(EXAMPLE_BIN + ".tmp", EXAMPLE_BIN)
 
 
 if __name__ == "__main__":
