@@ -299,6 +299,7 @@ def main():
             log(f"[bench] form {key}, {fs} steps")
             fr = time_lattice(cfg, fs, 50, diag_every=0)
             forms[key] = {"mlups": round(fr["mlups"], 1), "kernel_mlups": round(fr["kernel_mlups"], 1),
+                          "mflups": round(fr["mflups"], 1), "fluid_cells": fr["fluid_cells"],
                           "bytes_per_cell": fr["bytes_per_cell"], "achieved_gbs": round(fr["achieved_gbs"], 1),
                           "roofline_frac": round(fr["roofline_frac"], 4),
                           "frac_of_copy": round(fr["achieved_gbs"] / bs, 4) if bs else None}
