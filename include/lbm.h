@@ -249,7 +249,8 @@ int lbm_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *
 /* Measurement helper.                                                       */
 /* ------------------------------------------------------------------------ */
 
-/* Plain device copy of bytes (multiple of 16) from src_dev to dst_dev: the
+/* Plain device copy of bytes (multiple of 16) from src_dev to dst_dev (both
+ * 16-byte aligned, else LBM_EINVAL): the
  * device analogue of the STREAM copy the paper uses to measure the machine
  * bandwidth b_s of its roofline P_max = b_s / n_b (Section 5.2, Eq. (3)). */
 int lbm_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, void *stream);

@@ -454,6 +454,8 @@ int lbm_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, void *stre
 {
     if (!src_dev || !dst_dev) return fail(nullptr, LBM_EINVAL, "copy: NULL pointer");
     if (bytes % 16) return fail(nullptr, LBM_EINVAL, "copy: bytes must be a multiple of 16");
+    if (((uintptr_t)src_dev | (uintptr_t)dst_dev) & 15)
+        return fail(nullptr, LBM_EINVAL, "copy: src and dst must be 16-byte aligned");
     hipError_t e = launch_copy(src_dev, dst_dev, bytes, (hipStream_t)stream);
     return e == hipSuccess ? LBM_OK : hip_fail(nullptr, e, "stream_copy");
 }

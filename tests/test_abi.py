@@ -139,6 +139,7 @@ def test_create_rejects_before_device(L, case):
 def test_free_functions_reject(L):
     assert L.lbm_box_filter4(6, 8, 8, 1, 1, 1, None) == lbm.LBM_EINVAL
     assert L.lbm_stream_copy(0x1000, 0x2000, 15, None) == lbm.LBM_EINVAL
+    assert L.lbm_stream_copy(0x1004, 0x2000, 16, None) == lbm.LBM_EINVAL  # misaligned source
     assert L.lbm_mlp_forward(None, None, -1, None, None) == lbm.LBM_EINVAL
     assert L.lbm_mlp_adam(0x1000, 0x1000, 0x1000, 0x1000, 0, 1e-3, 0.9, 0.999, 1e-8, None) == lbm.LBM_EINVAL
     per = (ctypes.c_int32 * 3)(1, 0, 1)
