@@ -218,12 +218,13 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=65536)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval-coarse-steps", type=int, default=500)
+    ap.add_argument("--seed", type=int, default=1234, help="seed of the start state and of minibatch sampling")
     ap.add_argument("--out", default=None, help="write the JSON result here")
     a = ap.parse_args(argv)
     cfg = ClosureConfig(coarse=tuple(a.coarse), tau_c=a.tau_c, noise=a.noise, vortical_rms=a.vortical_rms,
                         vortical_wavelength=a.vortical_wavelength, spinup=a.spinup,
                         snapshots=a.snapshots, every=a.every, train_steps=a.train_steps, batch=a.batch, lr=a.lr,
-                        eval_coarse_steps=a.eval_coarse_steps)
+                        eval_coarse_steps=a.eval_coarse_steps, seed=a.seed)
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
