@@ -80,3 +80,60 @@ def test_et_refuses_the_learned_closure():
     with pytest.raises(lbm.LBMError) as exc:
         lbm.Lattice((16, 8, 8), closure="mlp", streaming="et")
     assert exc.value.code == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("q,storage,closure,collision", [
+    (27, "f32", "smagorinsky", "mrt"),
+    (19, "f16", "smagorinsky", "trt"),
+    (19, "bf16", "none", "mrt"),
+    (27, "f16", "none", "trt"),
+    (19, "f32", "smagorinsky", "mrt"),
+])
+def test_kernel_combinations(q, storage, closure, collision):
+    """Step-kernel instantiations that the other cases do not reach together:
+    solids, velocity / pressure / no-slip faces, a force, both streaming
+    schemes.  FP32 runs against the oracle (1e-5); 16-bit runs compare the
+    two schemes, which differ only by FP32 rounding order (the bound of
+    test_et_agrees_with_aa)."""
+    import oracle
+    from paper_2305_09910_amd import lbm
+    from test_gpu_parity import BCS, max_rel
+    shape = (24, 12, 10)
+    solid = np.zeros(shape[::-1], np.uint8)
+    solid[4:6, 3:6, 8:12] = 1
+    uw = np.zeros((6, 3))
+    uw[0] = (0.02, 0.0, 0.001)
+    bc = ("velocity", "pressure", "noslip", "noslip", "periodic", "periodic")
+    rates = (1.6, 1.75, 1.55, 1.65, 1.7) if q == 27 else None
+    kw = dict(q=q, tau=0.62, force=(1e-5, 0, 2e-6), bc=bc, u_bc=uw, solid=solid, storage=storage, closure=closure,
+              collision=collision, mrt_rates=rates)
+    print(f"[case] q={q} {storage} {closure} {collision}", flush=True)
+    a = lbm.Lattice(shape, streaming="aa", **kw)
+    e = lbm.Lattice(shape, streaming="et", **kw)
+    rho, u = inputs.uniform_flow(*shape, (0.02, 0.0, 0.0))
+    u += inputs.perturbation(u.shape, 0.004, seed=q)
+    u[:, solid == 1] = 0.0
+    for g in (a, e):
+        g.init_equilibrium(rho, u)
+        g.step(60)
+    fluid = solid == 0
+    if storage == "f32":
+        cl = {"none": oracle.CL_NONE, "smagorinsky": oracle.CL_SMAG}[closure]
+        o = oracle.Sim(q, shape, bc=tuple(BCS[b] for b in bc), tau=0.62, force=(1e-5, 0, 2e-6), u_bc=uw,
+                       solid=solid, closure=cl)
+        if collision == "mrt":
+            o.set_mrt(oracle.MRT_DHUMIERES if rates is None else rates)
+        o.init_equilibrium(rho, u)
+        o.step(60)
+        for g in (a, e):
+            assert max_rel(g.get_pdfs(), o.get_pdfs(), solid) <= 1e-5
+    else:
+        fa, fe = a.get_pdfs(), e.get_pdfs()
+        fl = torch.as_tensor(fluid, device=a.device)
+        w = torch.as_tensor(lbm_weights(q), device=a.device, dtype=torch.float64)[:, None, None, None]
+        dmax = float((fa - w)[:, fl].abs().max())
+        rel = 2.0 ** -10 if storage == "f16" else 2.0 ** -7
+        bound = 60 * 2 * rel * 2.0 ** np.floor(np.log2(dmax))
+        diff = float((fa - fe)[:, fl].abs().max())
+        print(f"max |f_aa - f_et| = {diff:.3e} (bound {bound:.3e})")
+        assert diff <= bound
