@@ -65,7 +65,7 @@ int totals_blocks();
 hipError_t launch_totals(const LatticeArgs &a, int q, int st, int odd, double *partial, double *final_out,
                          hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
-// operand table of the closure network (71 x 64 words) from its parameters
+// operand table of the closure network (63 x 64 words) from its parameters
 hipError_t launch_build_mlp_table(const float *params, uint32_t *table, hipStream_t s);
 
 // closure training path (lbm_closure.hip)

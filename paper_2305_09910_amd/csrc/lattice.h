@@ -388,9 +388,16 @@ __device__ inline void noneq_flux(const LatticeArgs &a, const float (&d)[Q], flo
     P[5] = pyz - M.rho * M.uy * M.uz + 0.5f * (M.uy * F2 + F1 * M.uz);
 }
 
+// The closures' square roots and quotients use the hardware square root and
+// reciprocal (within 1 ulp each): their operands are positive normal numbers,
+// and an ulp of a relaxation time is far below what the FP32 populations
+// resolve.
+__device__ inline float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+
 __device__ inline float flux_norm(const float (&P)[6])
 {
-    return sqrtf(P[0] * P[0] + P[1] * P[1] + P[2] * P[2] + 2.f * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]));
+    return __builtin_amdgcn_sqrtf(P[0] * P[0] + P[1] * P[1] + P[2] * P[2] +
+                                  2.f * (P[3] * P[3] + P[4] * P[4] + P[5] * P[5]));
 }
 
 // Hou et al. (1996) Smagorinsky relaxation time from |P_c|:
@@ -399,8 +406,16 @@ __device__ inline float flux_norm(const float (&P)[6])
 // has no cancellation in FP32 when a << tau^2.
 __device__ inline float smag_excess(float tau, float cs, float Qn, float rho)
 {
-    const float a = 18.f * 1.41421356237f * cs * cs * Qn / rho;
-    return 0.5f * a / (sqrtf(tau * tau + a) + tau);
+    const float a = 18.f * 1.41421356237f * cs * cs * Qn * rcp(rho);
+    return 0.5f * a * rcp(__builtin_amdgcn_sqrtf(tau * tau + a) + tau);
+}
+
+// TRT rates of a cell whose relaxation time is tt: omega+ = 1/tt and
+// omega- from the magic parameter, 1 / (1/2 + Lambda / (tt - 1/2)).
+__device__ inline void trt_rates(float tt, float magic, float &wp, float &wm)
+{
+    wp = rcp(tt);
+    wm = rcp(0.5f + magic * rcp(tt - 0.5f));
 }
 
 // keep: exchange each pair instead of colliding (solid lanes on the even
@@ -534,9 +549,7 @@ __device__ inline void relax_rates(const LatticeArgs &a, const float (&d)[Q], fl
     if constexpr (CL == CL_SMAG) {
         float P[6];
         noneq_flux<Q>(a, d, drho, M, P);
-        const float tt = a.tau + smag_excess(a.tau, a.cs, flux_norm(P), M.rho);
-        wp = 1.f / tt;
-        wm = 1.f / (0.5f + a.magic / (tt - 0.5f));
+        trt_rates(a.tau + smag_excess(a.tau, a.cs, flux_norm(P), M.rho), a.magic, wp, wm);
     }
 }
 

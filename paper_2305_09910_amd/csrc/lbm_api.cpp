@@ -10,7 +10,7 @@
 //   mask         n uint32 words (only with use_flags)
 //   totals       partial sums (1024 blocks x 5 doubles) and the final 5
 //   closure      MLP parameters (1313 + 24 FP32), their per-lane operand table
-//                (71 x 64 words) and a fallback counter
+//                (63 x 64 words) and a fallback counter
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -112,7 +112,7 @@ static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c)
     L->mlp = off;
     off += al256((MLP_NPARAM + MLP_NNORM) * sizeof(float));
     L->mlp_tab = off;
-    off += al256(71 * 64 * sizeof(uint32_t));
+    off += al256(63 * 64 * sizeof(uint32_t));
     L->fallback = off;
     off += 256;
     L->total = off;

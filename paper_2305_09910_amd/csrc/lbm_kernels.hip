@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collid
         const float tsm = a.tau + excess;
         float tt = tsm;
         if constexpr (CL == CL_MLP) {
-            const float ir = 1.f / M.rho;
+            const float ir = rcp(M.rho);
             float Pn[6], xf[6];
 #pragma unroll
             for (int k = 0; k < 6; ++k) Pn[k] = P[k] * ir;
@@ -121,14 +121,13 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collid
             float xin[6];
 #pragma unroll
             for (int k = 0; k < 6; ++k) xin[k] = inside ? xf[k] : a.mlp[P_MU + k];
-            const float dtau = softplus_f(mlp_forward_table(tab, xin, lane));
+            const float dtau = softplus_fast(mlp_forward_table(tab, xin, lane));
             const bool use = inside && isfinite(dtau);
             tt = use ? a.tau + dtau : tsm;
             const uint64_t fb = __ballot(active && !use);
             if (lane == 0 && fb) atomicAdd(a.fallbacks, (unsigned long long)__popcll(fb));
         }
-        wp = 1.f / tt;
-        wm = 1.f / (0.5f + a.magic / (tt - 0.5f));
+        trt_rates(tt, a.magic, wp, wm);
     }
     if constexpr (COLL == COLL_MRT)
         mrt_collide<Q>(a, d, drho, M, wp, keep);

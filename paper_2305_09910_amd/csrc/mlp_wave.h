@@ -21,6 +21,8 @@
 namespace lbm {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // parameter block (FP32): W1[32][6], b1[32], W2[32][32], b2[32], W3[32], b3,
@@ -33,14 +35,19 @@ __device__ inline uint16_t bf16_rne_bits(float v) { return __builtin_bit_cast(ui
 
 __device__ inline float bf16_round(float v) { return __uint_as_float((uint32_t)bf16_rne_bits(v) << 16); }
 
+// two values to bfloat16 (round to nearest even) in one v_cvt_pk_bf16_f32
+__device__ inline bf16x2 pack2(float a, float b)
+{
+    const f32x2 v = {a, b};
+    return __builtin_convertvector(v, bf16x2);
+}
+
+__device__ inline uint32_t pack2_bits(float a, float b) { return __builtin_bit_cast(uint32_t, pack2(a, b)); }
+
 __device__ inline bf16x4 pack4(float a, float b, float c, float d)
 {
-    bf16x4 r;
-    r.x = (short)bf16_rne_bits(a);
-    r.y = (short)bf16_rne_bits(b);
-    r.z = (short)bf16_rne_bits(c);
-    r.w = (short)bf16_rne_bits(d);
-    return r;
+    const uint64_t lo = pack2_bits(a, b), hi = pack2_bits(c, d);
+    return __builtin_bit_cast(bf16x4, lo | (hi << 32));
 }
 
 // row of the 32x32 result held by accumulator register r of lane l
@@ -75,6 +82,19 @@ __device__ inline float tanh_fast(float x)
 __device__ inline float softplus_f(float o) { return o > 20.f ? o : log1pf(__expf(o)); }
 
 __device__ inline float sigmoid_f(float o) { return 1.f / (1.f + __expf(-o)); }
+
+// softplus(o) = max(o, 0) + log1p(e) with e = exp(-|o|) <= 1, from the
+// hardware exp2, log2 and reciprocal.  log1p(e) is taken as
+// log(1 + e) * e / ((1 + e) - 1): the quotient cancels the rounding error of
+// 1 + e, so the result stays within a few ulp for every e (Goldberg 1991,
+// Theorem 4).  NaN in, NaN out; +inf in, +inf out.
+__device__ inline float softplus_fast(float o)
+{
+    const float e = __builtin_amdgcn_exp2f(-fabsf(o) * 1.4426950408889634f);
+    const float u = 1.f + e;
+    const float l = u == 1.f ? e : __builtin_amdgcn_logf(u) * 0.6931471805599453f * e * __builtin_amdgcn_rcpf(u - 1.f);
+    return fmaxf(o, 0.f) + l;
+}
 
 // Standardised inputs of this lane and the B operands of layer 1 for the
 // two sample blocks: block b holds samples 32b .. 32b+31 as columns; lane l
@@ -125,9 +145,11 @@ __device__ inline f32x16 bias16(const float *__restrict__ P, int off, int lane)
 //   k 2-9    A operands of layer 2, K-blocks 0-3 (4 bfloat16 each)
 //   k 10-25  b1 of the 16 accumulator rows of this lane
 //   k 26-41  b2 of the 16 accumulator rows
-//   k 42-57  W3 of the 16 accumulator rows, rounded to bfloat16
-//   k 58-63  mu, k 64-69 1/sigma, k 70 b3 (lane-uniform, replicated)
-constexpr int TAB_WORDS = 71;
+//   k 42-49  W3 of accumulator rows 2j and 2j+1 in entry 42 + j, as a
+//            bfloat16 pair (operand of v_dot2_f32_bf16)
+//   k 50-55  mu, k 56-61 1/sigma, k 62 b3 (lane-uniform, replicated)
+constexpr int TAB_W3 = 42, TAB_MU = 50, TAB_ISG = 56, TAB_B3 = 62;
+constexpr int TAB_WORDS = 63;
 
 __device__ inline void build_table_lane(const float *__restrict__ P, int lane, uint32_t *__restrict__ T)
 {
@@ -146,13 +168,14 @@ __device__ inline void build_table_lane(const float *__restrict__ P, int lane, u
     for (int r = 0; r < 16; ++r) {
         T[(10 + r) * 64 + lane] = __float_as_uint(P[P_B1 + drow(r, lane)]);
         T[(26 + r) * 64 + lane] = __float_as_uint(P[P_B2 + drow(r, lane)]);
-        T[(42 + r) * 64 + lane] = __float_as_uint(bf16_round(P[P_W3 + drow(r, lane)]));
     }
+    for (int j = 0; j < 8; ++j)
+        T[(TAB_W3 + j) * 64 + lane] = pack2_bits(P[P_W3 + drow(2 * j, lane)], P[P_W3 + drow(2 * j + 1, lane)]);
     for (int k = 0; k < 6; ++k) {
-        T[(58 + k) * 64 + lane] = __float_as_uint(P[P_MU + k]);
-        T[(64 + k) * 64 + lane] = __float_as_uint(1.f / P[P_SG + k]);
+        T[(TAB_MU + k) * 64 + lane] = __float_as_uint(P[P_MU + k]);
+        T[(TAB_ISG + k) * 64 + lane] = __float_as_uint(1.f / P[P_SG + k]);
     }
-    T[70 * 64 + lane] = __float_as_uint(P[P_B3]);
+    T[TAB_B3 * 64 + lane] = __float_as_uint(P[P_B3]);
 }
 
 __device__ inline bf16x4 tab4(const uint32_t *T, int k, int lane)
@@ -174,7 +197,7 @@ __device__ inline float mlp_forward_table(const uint32_t *T, const float (&x)[6]
 {
     float z[6], zp[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) z[k] = (x[k] - tabf(T, 58 + k, lane)) * tabf(T, 64 + k, lane);
+    for (int k = 0; k < 6; ++k) z[k] = (x[k] - tabf(T, TAB_MU + k, lane)) * tabf(T, TAB_ISG + k, lane);
 #pragma unroll
     for (int k = 0; k < 6; ++k) zp[k] = __shfl_xor(z[k], 32, 64);
     const bool hi = lane >= 32;
@@ -200,16 +223,18 @@ __device__ inline float mlp_forward_table(const uint32_t *T, const float (&x)[6]
         g0 = mfma32(a2, pack4(h0[4 * kb], h0[4 * kb + 1], h0[4 * kb + 2], h0[4 * kb + 3]), g0);
         g1 = mfma32(a2, pack4(h1[4 * kb], h1[4 * kb + 1], h1[4 * kb + 2], h1[4 * kb + 3]), g1);
     }
+    // third layer: bfloat16 activation pairs against bfloat16 weight pairs,
+    // products exact, FP32 sums (v_dot2_f32_bf16)
     float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const float w = tabf(T, 42 + r, lane);
-        s0 += w * bf16_round(tanh_fast(g0[r]));
-        s1 += w * bf16_round(tanh_fast(g1[r]));
+    for (int j = 0; j < 8; ++j) {
+        const bf16x2 w = __builtin_bit_cast(bf16x2, T[(TAB_W3 + j) * 64 + lane]);
+        s0 = __builtin_amdgcn_fdot2_f32_bf16(pack2(tanh_fast(g0[2 * j]), tanh_fast(g0[2 * j + 1])), w, s0, false);
+        s1 = __builtin_amdgcn_fdot2_f32_bf16(pack2(tanh_fast(g1[2 * j]), tanh_fast(g1[2 * j + 1])), w, s1, false);
     }
     s0 += __shfl_xor(s0, 32, 64);
     s1 += __shfl_xor(s1, 32, 64);
-    return (hi ? s1 : s0) + tabf(T, 70, lane);
+    return (hi ? s1 : s0) + tabf(T, TAB_B3, lane);
 }
 
 // Forward pass.  h1_* and h2_* receive the FP32 activations of both blocks
@@ -269,11 +294,12 @@ __device__ inline void closure_features(const float (&Pn)[6], float rho, float t
     const float tr = Pn[0] + Pn[1] + Pn[2];
     const float d0 = Pn[0] - tr * (1.f / 3.f), d1 = Pn[1] - tr * (1.f / 3.f), d2 = Pn[2] - tr * (1.f / 3.f);
     const float xy = Pn[3], xz = Pn[4], yz = Pn[5];
-    const float nd = sqrtf(d0 * d0 + d1 * d1 + d2 * d2 + 2.f * (xy * xy + xz * xz + yz * yz));
+    const float nd = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1 + d2 * d2 + 2.f * (xy * xy + xz * xz + yz * yz));
     const float det = d0 * (d1 * d2 - yz * yz) - xy * (xy * d2 - yz * xz) + xz * (xy * yz - d1 * xz);
     x[0] = tr;
     x[1] = nd;
-    x[2] = cbrtf(det);
+    // cube root as sign * 2^(log2|det| / 3) (hardware log2 and exp2; 0 -> 0)
+    x[2] = copysignf(__builtin_amdgcn_exp2f(__builtin_amdgcn_logf(fabsf(det)) * (1.f / 3.f)), det);
     x[3] = rho - 1.f;
     x[4] = smag_excess;
     x[5] = tau;
@@ -283,7 +309,7 @@ __device__ inline bool features_in_range(const float *__restrict__ P, const floa
 {
     bool ok = true;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) ok = ok && (x[k] >= P[P_LO + k]) && (x[k] <= P[P_HI + k]);
+    for (int k = 0; k < 6; ++k) ok &= (x[k] >= P[P_LO + k]) & (x[k] <= P[P_HI + k]);
     return ok;
 }
 
