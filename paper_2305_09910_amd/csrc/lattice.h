@@ -58,7 +58,7 @@ namespace lbm {
 // loaded and stored with the nontemporal hint (no reuse; it should not
 // displace other lines).  Lines read with a +-1 shift along x are shared
 // with the neighbouring wavefront in the same workgroup, so those keep the
-// normal policy and meet in L2.
+// normal policy and meet in the CU's L1 (or in L2).
 template <bool NT, class T>
 __device__ inline T ld_pop(const T *p)
 {
