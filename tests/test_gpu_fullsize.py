@@ -112,6 +112,63 @@ def test_two_steps_sampled_against_probe(name, storage, collision):
     torch.cuda.empty_cache()
 
 
+def _timing_network(seed=9):
+    """The seeded network the benchmark times the fused closure with: smooth
+    weights, inputs standardised to unit scale, unbounded trusted range."""
+    rng = np.random.default_rng(seed)
+    p = np.concatenate([rng.normal(0, 0.3, 192), rng.normal(0, 0.1, 32), rng.normal(0, 0.15, 1024),
+                        rng.normal(0, 0.1, 32), rng.normal(0, 0.1, 32), [-5.0]])
+    norm = np.concatenate([np.zeros(6), [1e-3, 1e-3, 1e-3, 1e-2, 1e-2, 1.0], np.full(6, -1e30), np.full(6, 1e30)])
+    return p.astype(np.float32), norm.astype(np.float32)
+
+
+@pytest.mark.parametrize("name,storage,streaming,closure", [
+    ("channel_256x128x128", "f32", "aa", "smagorinsky"),
+    ("channel_256x128x128", "f32", "aa", "mlp"),
+    ("channel_512x256x256", "f32", "aa", "mlp"),
+    ("channel_256x128x128", "f32", "et", "none"),
+    ("channel_512x256x256", "f32", "et", "none"),
+    ("channel_512x256x256", "f16", "et", "none"),
+    ("obstacles_384_d3q27", "f32", "et", "none"),
+])
+def test_closures_and_esoteric_twist_sampled_against_probe(name, storage, streaming, closure):
+    """The closure forms and the Esoteric Twist forms at their benchmark
+    shapes: two steps, sampled cells against the oracle's probe."""
+    from paper_2305_09910_amd import lbm
+    cfg, rho, u = _case(name)
+    print(f"[case] {name} storage={storage} streaming={streaming} closure={closure}", flush=True)
+    g = lbm.Lattice(cfg["shape"], q=cfg["q"], tau=cfg["tau"], force=cfg["force"], bc=cfg["bc"], u_bc=cfg["u_bc"],
+                    solid=cfg["solid"], storage=storage, closure=closure, cs=0.1, streaming=streaming)
+    ocl = {"none": oracle.CL_NONE, "smagorinsky": oracle.CL_SMAG, "mlp": oracle.CL_MLP}[closure]
+    o = oracle.Sim(cfg["q"], cfg["shape"], bc=tuple(BCS[b] for b in cfg["bc"]), tau=cfg["tau"], force=cfg["force"],
+                   u_bc=cfg["u_bc"], solid=cfg["solid"], closure=ocl, cs=0.1)
+    if closure == "mlp":
+        p, norm = _timing_network()
+        g.set_closure_weights(np.concatenate([p, norm]))
+        o.set_mlp(p, norm)
+    g.init_equilibrium(rho, u)
+    g.step(2)
+    cells = _samples(cfg["shape"], cfg["solid"])
+    got = g.gather(cells).cpu().numpy()
+    ref = o.probe(rho, u, 2, cells)
+    c, w, _ = oracle.velocity_set(cfg["q"])
+    err = np.abs(got - ref)
+    if storage == "f32":
+        # the closures' FP32 features and rates (hardware reciprocal and
+        # square root) sit a few ulp from the oracle's FP64 values
+        bound = (1e-6 if closure == "none" else 2e-6) * np.abs(ref)
+    else:
+        unit = 2.0 ** -11
+        dmax = np.abs(ref - w[None, :]).max()
+        bound = 3 * unit * dmax + 1e-7 * np.abs(ref)
+    print(name, storage, streaming, closure, "max abs err", err.max(), "max rel", (err / np.abs(ref)).max())
+    assert np.all(err <= bound)
+    if closure == "mlp":
+        assert g.closure_fallbacks() == 0
+    del g
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("name", ["channel_256x128x128", "channel_512x256x256"])
 def test_mass_conserved_and_deterministic_at_full_size(name):
     from paper_2305_09910_amd import lbm
