@@ -37,6 +37,18 @@ INOUT_X = ("velocity", "pressure", "periodic", "periodic", "periodic", "periodic
 BYTES = {"f32": 4, "f16": 2, "bf16": 2}
 
 
+def bytes_per_cell(q, value_bytes, mask=False):
+    """Algorithmic HBM bytes of one cell update (the paper's n_b, Section 5.2):
+    each of the q populations is read once and written once, plus the solid
+    flag of the cell when the domain has one."""
+    return 2 * q * value_bytes + (1 if mask else 0)
+
+
+def roofline_mlups(bandwidth_bytes_per_s, nb):
+    """Bandwidth bound P_max = b_s / n_b in lattice updates per second, as MLUPS."""
+    return bandwidth_bytes_per_s / nb / 1e6
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -161,7 +173,7 @@ def time_lattice(cfg, steps, warmup, diag_every=1000):
                ms_per_step=1e3 * wall / steps, kernel_ms=kern_ms / steps,
                mlups=n * steps / wall / 1e6, kernel_mlups=n * steps / (kern_ms * 1e-3) / 1e6,
                mflups=nfluid * steps / wall / 1e6, finite=mass_ok)
-    nb = 2 * cfg["q"] * BYTES[cfg["storage"]] + (1 if cfg["solid"] is not None else 0)
+    nb = bytes_per_cell(cfg["q"], BYTES[cfg["storage"]], cfg["solid"] is not None)
     res["bytes_per_cell"] = nb
     res["achieved_gbs"] = nb * n / (res["kernel_ms"] * 1e-3) / 1e9
     res["roofline_frac"] = res["achieved_gbs"] / HBM_PEAK_GBS
