@@ -81,6 +81,7 @@ def demo_closure_weights(seed=9):
 
 
 KERNEL_SOURCES = ["paper_2305_09910_amd/csrc/lbm_kernels.hip", "paper_2305_09910_amd/csrc/lbm_et.hip",
+                  "paper_2305_09910_amd/csrc/lbm_sparse.hip",
                   "paper_2305_09910_amd/csrc/lattice.h",
                   "paper_2305_09910_amd/csrc/stencil.h", "paper_2305_09910_amd/csrc/internal.h",
                   "paper_2305_09910_amd/csrc/mlp_wave.h"]

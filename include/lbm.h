@@ -97,9 +97,15 @@ enum { LBM_COLL_TRT = 0, LBM_COLL_MRT = 1 };
  *     i and opposite(i) from step to step.  Each non-periodic axis gets one
  *     ghost layer beyond its + face in the store (it holds the populations
  *     that face returns).  Not combinable with the learned closure.
- * Both give the same populations up to FP32 rounding order (none: the same
+ * AA_SPARSE: the AA pattern over the fluid cells only (sparse indirect
+ *     addressing, for domains that solids fill to a large part): fluid cells
+ *     are stored compacted in row order, and a table of the q-1 neighbours of
+ *     each fluid cell (4 bytes each) serves the odd steps.  The population
+ *     store and the table are sized by the fluid cells (see
+ *     lbm_workspace_bytes_flags).  Not combinable with the learned closure.
+ * All give the same populations up to FP32 rounding order (the same
  * arithmetic runs on the same values). */
-enum { LBM_STREAM_AA = 0, LBM_STREAM_ET = 1 };
+enum { LBM_STREAM_AA = 0, LBM_STREAM_ET = 1, LBM_STREAM_AA_SPARSE = 2 };
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -129,8 +135,14 @@ void lbm_domain_defaults(lbm_domain *d);
 
 /* Bytes of device workspace a context needs for domain d and the stencil
  * (19 or 27).  Only nx, ny, nz, storage, closure, use_flags, streaming and
- * (for the ghost layers of the Esoteric Twist) bc are read. */
+ * (for the ghost layers of the Esoteric Twist) bc are read.  With sparse
+ * addressing this is the bound for a domain without solids. */
 int lbm_workspace_bytes(const lbm_domain *d, int stencil, size_t *out);
+
+/* As lbm_workspace_bytes, for the solid flags that lbm_create will get
+ * (host, one byte per cell, nullable): with sparse addressing the stores are
+ * sized by the fluid cells; otherwise the same value. */
+int lbm_workspace_bytes_flags(const lbm_domain *d, int stencil, const uint8_t *flags, size_t *out);
 
 /*
  * Create a context.  tau > 1/2 is the molecular relaxation time
@@ -185,8 +197,9 @@ int lbm_totals(lbm_ctx *ctx, double *mass, double mom[3]);
 
 /* Bytes of the raw population store (for checkpoints): q rows of sx cells
  * per stored row, sx = nx rounded up to whole 128-byte lines, with the
- * Esoteric Twist's ghost layers included.  Its layout is internal; only
- * lbm_load_state of a context with the same domain reads it back. */
+ * Esoteric Twist's ghost layers included; with sparse addressing q values
+ * per fluid cell, in chunks of 64.  Its layout is internal; only
+ * lbm_load_state of a context with the same domain and flags reads it back. */
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *out);
 
 /* Copy the raw state to dst_dev (lbm_state_bytes bytes) and report the

@@ -17,6 +17,17 @@ enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
 // only) as solid.
 constexpr uint32_t SELF_SOLID = 0x80000000u;
 
+// Sparse addressing: fluid cells k = 0 .. nf-1 in row order, stored in
+// chunks of 64 (one wavefront): population i of cell k at
+// ((k / 64) q + i) 64 + k % 64, neighbour-table entry j (1 <= j < q) at
+// ((k / 64) (q - 1) + j - 1) 64 + k % 64.  A table entry is the fluid index
+// of the neighbour x + c_j, or NB_SOLID when that neighbour is solid, or
+// NB_FACE0 + f when the link leaves through non-periodic face f (the face
+// that decides the link's boundary condition).
+constexpr int SP_CHUNK = 64;
+constexpr uint32_t NB_FACE0 = 0xFFFFFFF0u;
+constexpr uint32_t NB_SOLID = 0xFFFFFFFFu;
+
 // MLP closure parameter block in device memory (FP32), see lbm.h.
 constexpr int MLP_NPARAM = 1313;
 constexpr int MLP_NNORM = 24;
@@ -30,6 +41,10 @@ struct LatticeArgs {
     int sx, sy;              // cells per stored row and rows per stored plane: nx, ny, or one more
                              // for the ghost layer of the Esoteric Twist on a non-periodic + face
     int et;                  // streaming scheme: 0 AA pattern, 1 Esoteric Twist
+    int sp;                  // sparse addressing: the AA pattern over the fluid cells only
+    uint32_t nf;             // fluid cells (sparse addressing)
+    const int32_t *fmap;     // [n] fluid index of each cell, -1 for solid cells (sparse addressing)
+    const uint32_t *nbt;     // neighbour table [chunk][q - 1][64] (sparse addressing)
     int per[3];              // axis periodic?
     int bc[6];               // face kinds
     int any_vp;              // any velocity / pressure face
@@ -54,6 +69,11 @@ hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, 
 hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
 // Esoteric Twist step (lbm_et.hip); no learned closure
 hipError_t launch_step_et(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
+// sparse addressing (lbm_sparse.hip): neighbour table from the fluid map and
+// the fluid cells' linear indices, and the step; no learned closure
+hipError_t launch_build_sparse_table(const LatticeArgs &a, int q, const uint32_t *fcell, uint32_t *table,
+                                     hipStream_t s);
+hipError_t launch_step_sparse(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
 hipError_t launch_init_eq(const LatticeArgs &a, int q, int st, const double *rho, const double *u, hipStream_t s);
 hipError_t launch_set_pdfs(const LatticeArgs &a, int q, int st, const double *f, hipStream_t s);
 hipError_t launch_get_pdfs(const LatticeArgs &a, int q, int st, int odd, double *f, hipStream_t s);

@@ -1,7 +1,8 @@
-// lattice.h -- device-side core shared by the stream-collide kernels of both
-// streaming schemes (lbm_kernels.hip: AA pattern and the state kernels;
-// lbm_et.hip: Esoteric Twist): storage formats, cell geometry, population
-// addressing, canonical reads, collision operators and wall values.
+// lattice.h -- device-side core shared by the stream-collide kernels of every
+// scheme (lbm_kernels.hip: AA pattern and the state kernels; lbm_et.hip:
+// Esoteric Twist; lbm_sparse.hip: AA pattern over the fluid cells only):
+// storage formats, cell geometry, population addressing, canonical reads,
+// collision operators and wall values.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -237,6 +238,20 @@ __device__ inline int deciding_face(const LatticeArgs &a, const Geom &g, int dx,
     return best;
 }
 
+// sparse addressing: population i of fluid cell k, and neighbour-table entry
+// j of fluid cell k
+template <int Q>
+__device__ inline uint64_t sp_index(uint32_t k, int i)
+{
+    return ((uint64_t)(k / SP_CHUNK) * Q + (uint32_t)i) * SP_CHUNK + k % SP_CHUNK;
+}
+
+template <int Q>
+__device__ inline uint64_t sp_table(uint32_t k, int j)
+{
+    return ((uint64_t)(k / SP_CHUNK) * (Q - 1) + (uint32_t)(j - 1)) * SP_CHUNK + k % SP_CHUNK;
+}
+
 // ---------------------------------------------------------------------------
 // canonical read (shared by the step kernel and every state reader)
 // ---------------------------------------------------------------------------
@@ -245,6 +260,26 @@ __device__ inline void load_canonical(const LatticeArgs &a, const Geom &g, uint3
 {
     using S = Store<ST>;
     const typename S::T *A = (const typename S::T *)a.pdf;
+    if (a.sp) {
+        // sparse addressing (fluid cells only): the AA pattern over the
+        // fluid index; after an odd number of steps f_i sits in slot
+        // opposite(i) of the neighbour x - c_i, or in the cell's own slot i
+        // when that link is cut
+        const int32_t kf = a.fmap[g.c];
+        if (kf < 0) {  // solid cell: nothing stored
+#pragma unroll
+            for (int i = 0; i < Q; ++i) d[i] = 0.f;
+            return;
+        }
+        const uint32_t k = (uint32_t)kf;
+        d[0] = S::ld(A + sp_index<Q>(k, 0));
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const uint32_t t = odd ? a.nbt[sp_table<Q>(k, opp(i))] : NB_FACE0;
+            d[i] = S::ld(A + (t >= NB_FACE0 ? sp_index<Q>(k, i) : sp_index<Q>(t, opp(i))));
+        }
+        return;
+    }
     if (a.et) {
         // Esoteric Twist: f_i(x) sits at x + max(-c_i, 0) in slot i after an
         // even number of steps, slot opposite(i) after an odd number, cut
@@ -530,10 +565,12 @@ __device__ inline void mrt_collide(const LatticeArgs &a, float (&d)[Q], float dr
     });
 }
 
-// Storage index of f_i(x) after zero steps (either streaming scheme).
+// Storage index of f_i(x) after zero steps (any scheme; with sparse
+// addressing only for fluid cells).
 template <int Q>
 __device__ inline uint64_t index_t0(const LatticeArgs &a, const Geom &g, int i)
 {
+    if (a.sp) return sp_index<Q>((uint32_t)a.fmap[g.c], i);
     if (a.et) return et_index<Q>(a, g, i, cdir(i, 0) < 0, cdir(i, 1) < 0, cdir(i, 2) < 0);
     return pidx<Q>(a, i, g.row, g.x);
 }

@@ -6,8 +6,11 @@
 // aligned):
 //   populations  q * n storage elements, [z][y][q][x] (rows of q direction segments);
 //                with the Esoteric Twist each non-periodic axis has one more
-//                cell (the ghost layer beyond its + face)
+//                cell (the ghost layer beyond its + face); with sparse
+//                addressing q * nf elements in chunks of 64 fluid cells
 //   mask         n uint32 words (only with use_flags)
+//   sparse       (sparse addressing only) fluid map (n int32), fluid cells'
+//                linear indices (nf uint32) and neighbour table ((q-1) * nf uint32)
 //   totals       partial sums (1024 blocks x 5 doubles) and the final 5
 //   closure      MLP parameters (1313 + 24 FP32), their per-lane operand table
 //                (63 x 64 words) and a fallback counter
@@ -68,11 +71,13 @@ static int hip_fail(lbm_ctx *c, hipError_t e, const char *what)
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t pdf, mask, partial, final_out, mlp, mlp_tab, fallback, total, pdf_bytes;
+    size_t pdf, mask, fmap, fcell, nbt, partial, final_out, mlp, mlp_tab, fallback, total, pdf_bytes;
     int sx, sy, sz;  // cells of the population store per axis
 };
 
-static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c)
+// nf: fluid cells, which size the stores of sparse addressing (the cell
+// count when the flags are not known: an upper bound)
+static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c, int64_t nf = -1)
 {
     if (!d) return fail(c, LBM_EINVAL, "domain is NULL");
     if (q != 19 && q != 27) return fail(c, LBM_EINVAL, "stencil must be 19 or 27, got %d", q);
@@ -82,7 +87,7 @@ static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c)
         return fail(c, LBM_EINVAL, "unknown storage %d", d->storage);
     if (d->closure < LBM_LES_NONE || d->closure > LBM_LES_MLP)
         return fail(c, LBM_EINVAL, "unknown closure %d", d->closure);
-    if (d->streaming != LBM_STREAM_AA && d->streaming != LBM_STREAM_ET)
+    if (d->streaming != LBM_STREAM_AA && d->streaming != LBM_STREAM_ET && d->streaming != LBM_STREAM_AA_SPARSE)
         return fail(c, LBM_EINVAL, "unknown streaming scheme %d", d->streaming);
     const uint64_t n = (uint64_t)d->nx * (uint64_t)d->ny * (uint64_t)d->nz;
     if (n >= (1ull << 31)) return fail(c, LBM_ENOMEM, "domain of %llu cells exceeds 2^31 cells", (unsigned long long)n);
@@ -99,12 +104,23 @@ static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c)
     const uint64_t ns = (uint64_t)L->sx * (uint64_t)L->sy * (uint64_t)L->sz;
     if (ns >= (1ull << 31))
         return fail(c, LBM_ENOMEM, "store of %llu cells exceeds 2^31 cells", (unsigned long long)ns);
+    const bool sp = d->streaming == LBM_STREAM_AA_SPARSE;
+    if (nf < 0 || nf > (int64_t)n) nf = (int64_t)n;
+    const uint64_t chunks = ((uint64_t)nf + SP_CHUNK - 1) / SP_CHUNK;
     size_t off = 0;
     L->pdf = off;
-    L->pdf_bytes = (size_t)q * ns * elem;
+    L->pdf_bytes = sp ? (size_t)q * chunks * SP_CHUNK * elem : (size_t)q * ns * elem;
     off += al256(L->pdf_bytes);
     L->mask = off;
     if (d->use_flags) off += al256(4 * n);
+    L->fmap = L->fcell = L->nbt = off;
+    if (sp) {
+        off += al256(4 * n);
+        L->fcell = off;
+        off += al256(4 * chunks * SP_CHUNK);
+        L->nbt = off;
+        off += al256((size_t)4 * (q - 1) * chunks * SP_CHUNK);
+    }
     L->partial = off;
     off += al256((size_t)totals_blocks() * 5 * sizeof(double));
     L->final_out = off;
@@ -148,6 +164,26 @@ int lbm_workspace_bytes(const lbm_domain *d, int stencil, size_t *out)
     return LBM_OK;
 }
 
+static int64_t count_fluid(const lbm_domain *d, const uint8_t *flags)
+{
+    const int64_t n = (int64_t)d->nx * d->ny * d->nz;
+    if (!flags) return n;
+    int64_t nf = 0;
+    for (int64_t k = 0; k < n; ++k) nf += flags[k] == 0;
+    return nf;
+}
+
+int lbm_workspace_bytes_flags(const lbm_domain *d, int stencil, const uint8_t *flags, size_t *out)
+{
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    if (!d) return fail(nullptr, LBM_EINVAL, "domain is NULL");
+    Layout L;
+    int rc = make_layout(d, stencil, &L, nullptr, count_fluid(d, flags));
+    if (rc) return rc;
+    *out = L.total;
+    return LBM_OK;
+}
+
 int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double tau, const double force[3],
                lbm_ctx **out)
 {
@@ -156,6 +192,10 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     Layout L;
     int rc = make_layout(d, stencil, &L, nullptr);
     if (rc) return rc;
+    const bool sp = d->streaming == LBM_STREAM_AA_SPARSE;
+    if (flags && !d->use_flags) return fail(nullptr, LBM_EINVAL, "flags given but domain.use_flags is 0");
+    const int64_t nf = count_fluid(d, flags);
+    if (sp && (rc = make_layout(d, stencil, &L, nullptr, nf))) return rc;  // stores sized by the fluid cells
     if (!(tau > 0.5) || !isfinite(tau)) return fail(nullptr, LBM_EINVAL, "tau must be > 1/2 (got %g)", tau);
     if (!(d->magic > 0.0) || !isfinite(d->magic)) return fail(nullptr, LBM_EINVAL, "magic must be > 0");
     if (d->closure != LBM_LES_NONE && !(d->cs_smag >= 0.0)) return fail(nullptr, LBM_EINVAL, "cs_smag must be >= 0");
@@ -165,11 +205,10 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     for (int a = 0; a < 3; ++a)
         if ((d->bc[2 * a] == LBM_BC_PERIODIC) != (d->bc[2 * a + 1] == LBM_BC_PERIODIC))
             return fail(nullptr, LBM_EINVAL, "axis %d: a periodic face needs a periodic opposite face", a);
-    if (flags && !d->use_flags) return fail(nullptr, LBM_EINVAL, "flags given but domain.use_flags is 0");
     if (d->collision != LBM_COLL_TRT && d->collision != LBM_COLL_MRT)
         return fail(nullptr, LBM_EINVAL, "unknown collision %d", d->collision);
-    if (d->streaming == LBM_STREAM_ET && d->closure == LBM_LES_MLP)
-        return fail(nullptr, LBM_EINVAL, "the learned closure runs with AA streaming only");
+    if (d->streaming != LBM_STREAM_AA && d->closure == LBM_LES_MLP)
+        return fail(nullptr, LBM_EINVAL, "the learned closure runs with dense AA streaming only");
     if (d->collision == LBM_COLL_MRT) {
         if (d->closure == LBM_LES_MLP) return fail(nullptr, LBM_EINVAL, "the MLP closure runs with TRT only");
         for (int k = 0; k < 5; ++k)
@@ -212,6 +251,10 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     a.sx = L.sx;
     a.sy = L.sy;
     a.et = d->streaming == LBM_STREAM_ET;
+    a.sp = sp;
+    a.nf = (uint32_t)nf;
+    a.fmap = sp ? (const int32_t *)(c->ws + L.fmap) : nullptr;
+    a.nbt = sp ? (const uint32_t *)(c->ws + L.nbt) : nullptr;
     for (int k = 0; k < 3; ++k) a.per[k] = d->bc[2 * k] == LBM_BC_PERIODIC;
     a.any_vp = 0;
     for (int f = 0; f < 6; ++f) {
@@ -232,20 +275,47 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     c->mlp_tab = (uint32_t *)(c->ws + L.mlp_tab);
     a.fallbacks = c->fallbacks;
 
-    c->nfluid = (int64_t)a.n;
+    c->nfluid = nf;
     hipError_t e = hipMemsetAsync(c->fallbacks, 0, sizeof(unsigned long long), c->stream);
     if (e == hipSuccess && c->mask) {
-        if (flags) {
-            int64_t solid = 0;
-            for (uint32_t k = 0; k < a.n; ++k) solid += flags[k] != 0;
-            c->nfluid -= solid;
-            // stage the flags in the (still undefined) population region
-            e = hipMemcpyAsync(a.pdf, flags, a.n, hipMemcpyHostToDevice, c->stream);
-            if (e == hipSuccess) e = launch_build_mask(a, stencil, (const uint8_t *)a.pdf, c->mask, c->stream);
-        } else {
-            e = hipMemsetAsync(a.pdf, 0, a.n, c->stream);
-            if (e == hipSuccess) e = launch_build_mask(a, stencil, (const uint8_t *)a.pdf, c->mask, c->stream);
+        // stage the flags in a region that is still undefined and holds at
+        // least n bytes: the population store, or the fluid map (sparse)
+        uint8_t *stage = (uint8_t *)(sp ? c->ws + L.fmap : a.pdf);
+        if (flags)
+            e = hipMemcpyAsync(stage, flags, a.n, hipMemcpyHostToDevice, c->stream);
+        else
+            e = hipMemsetAsync(stage, 0, a.n, c->stream);
+        if (e == hipSuccess) e = launch_build_mask(a, stencil, stage, c->mask, c->stream);
+    }
+    if (e == hipSuccess && sp) {
+        // fluid index of every cell (row order) and the linear index of every
+        // fluid cell; the neighbour table is built from them on the device
+        int32_t *fmap = new (std::nothrow) int32_t[a.n];
+        uint32_t *fcell = new (std::nothrow) uint32_t[nf > 0 ? nf : 1];
+        if (!fmap || !fcell) {
+            delete[] fmap;
+            delete[] fcell;
+            delete c;
+            return fail(nullptr, LBM_ENOMEM, "out of host memory for the fluid map");
         }
+        uint32_t k = 0;
+        for (uint32_t cell = 0; cell < a.n; ++cell) {
+            if (flags && flags[cell]) {
+                fmap[cell] = -1;
+            } else {
+                fmap[cell] = (int32_t)k;
+                fcell[k++] = cell;
+            }
+        }
+        e = hipMemcpyAsync(c->ws + L.fmap, fmap, (size_t)4 * a.n, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && nf > 0)
+            e = hipMemcpyAsync(c->ws + L.fcell, fcell, (size_t)4 * nf, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = launch_build_sparse_table(a, stencil, (const uint32_t *)(c->ws + L.fcell), (uint32_t *)(c->ws + L.nbt),
+                                          c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // before the host arrays go
+        delete[] fmap;
+        delete[] fcell;
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
@@ -308,8 +378,9 @@ int lbm_step(lbm_ctx *c, int64_t n)
         return fail(c, LBM_ESTATE, "MLP closure selected but lbm_set_closure_weights was not called");
     for (int64_t k = 0; k < n; ++k) {
         const int odd = (int)(c->time & 1);
-        hipError_t e = c->a.et ? launch_step_et(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream)
-                               : launch_step(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream);
+        hipError_t e = c->a.sp   ? launch_step_sparse(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream)
+                       : c->a.et ? launch_step_et(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream)
+                                 : launch_step(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "stream_collide launch");
         ++c->time;
     }

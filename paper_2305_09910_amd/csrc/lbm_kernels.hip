@@ -197,6 +197,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_init_eq(LatticeArgs a, const
     if (x >= a.nx || y >= a.ny) return;
     const Geom g = make_geom(a, x, y, z);
     const bool solid = a.mask && (a.mask[g.c] & SELF_SOLID);
+    if (a.sp && a.fmap[g.c] < 0) return;  // sparse addressing stores fluid cells only
     const double r = rho[g.c], ux = u[g.c], uy = u[(uint64_t)a.n + g.c], uz = u[2 * (uint64_t)a.n + g.c];
     const double usq = ux * ux + uy * uy + uz * uz;
     typename S::T *A = (typename S::T *)a.pdf;
@@ -217,6 +218,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_set_pdfs(LatticeArgs a, cons
     const int z = blockIdx.z;
     if (x >= a.nx || y >= a.ny) return;
     const Geom g = make_geom(a, x, y, z);
+    if (a.sp && a.fmap[g.c] < 0) return;  // sparse addressing stores fluid cells only
     typename S::T *A = (typename S::T *)a.pdf;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {

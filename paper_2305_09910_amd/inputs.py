@@ -105,6 +105,37 @@ def spheres(nx: int, ny: int, nz: int, fill: float = 0.10, rmin: float = 6.0, rm
     return mask, acc
 
 
+def porous(nx: int, ny: int, nz: int, solid_fraction: float = 0.7, rmin: float = 3.0, rmax: float = 8.0,
+           seed: int = 77):
+    """Periodic porous medium of random overlapping solid spheres; returns a
+    uint8 mask [nz, ny, nx].
+
+    Radii are uniform reals in [rmin, rmax] and centres uniform reals in the
+    box; a cell (i, j, k) is solid iff its periodic distance to some centre
+    is <= r.  Spheres are added until the solid voxel fraction reaches
+    `solid_fraction`, so the medium wraps around every face.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    total = nx * ny * nz
+    solid = 0
+    while solid < solid_fraction * total:
+        r = rng.uniform(rmin, rmax)
+        xc, yc, zc = rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz)
+        R = int(math.ceil(r))
+        ix = np.arange(int(math.floor(xc)) - R, int(math.floor(xc)) + R + 2)
+        iy = np.arange(int(math.floor(yc)) - R, int(math.floor(yc)) + R + 2)
+        iz = np.arange(int(math.floor(zc)) - R, int(math.floor(zc)) + R + 2)
+        inside = ((iz[:, None, None] - zc) ** 2 + (iy[None, :, None] - yc) ** 2 + (ix[None, None, :] - xc) ** 2
+                  <= r * r)
+        kz, ky, kx = np.nonzero(inside)
+        cells = np.unique(((iz[kz] % nz) * ny + iy[ky] % ny) * nx + ix[kx] % nx)  # wrapped, each once
+        flat = mask.reshape(-1)
+        solid += int(np.count_nonzero(flat[cells] == 0))
+        flat[cells] = 1
+    return mask
+
+
 def uniform_flow(nx: int, ny: int, nz: int, u=(0.04, 0.0, 0.0), rho: float = 1.0):
     shape = (nz, ny, nx)
     uu = np.zeros((3,) + shape)

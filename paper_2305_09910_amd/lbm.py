@@ -21,14 +21,14 @@ BC = {"periodic": 0, "noslip": 1, "velocity": 2, "pressure": 3}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 CLOSURE = {"none": 0, "smagorinsky": 1, "mlp": 2}
 COLLISION = {"trt": 0, "mrt": 1}
-STREAMING = {"aa": 0, "et": 1}
+STREAMING = {"aa": 0, "et": 1, "sparse": 2}
 MRT_DEFAULT_RATES = (1.19, 1.4, 1.2, 1.4, 1.98)
 MLP_NPARAM, MLP_NNORM = 1313, 24
 
 _ERRNAMES = {-1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_ENONFINITE", -5: "LBM_ESTATE"}
 
 EXPORTED = [
-    "lbm_domain_defaults", "lbm_workspace_bytes", "lbm_create", "lbm_destroy", "lbm_last_error",
+    "lbm_domain_defaults", "lbm_workspace_bytes", "lbm_workspace_bytes_flags", "lbm_create", "lbm_destroy", "lbm_last_error",
     "lbm_init_equilibrium", "lbm_set_pdfs", "lbm_get_pdfs", "lbm_gather_pdfs", "lbm_step", "lbm_time",
     "lbm_moments", "lbm_totals", "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
     "lbm_set_closure_weights", "lbm_closure_fallbacks", "lbm_box_filter4", "lbm_closure_dataset",
@@ -71,6 +71,7 @@ def lib():
         sig = {
             "lbm_domain_defaults": (None, [DP]),
             "lbm_workspace_bytes": (ctypes.c_int, [DP, ctypes.c_int, ctypes.POINTER(SZ)]),
+            "lbm_workspace_bytes_flags": (ctypes.c_int, [DP, ctypes.c_int, P, ctypes.POINTER(SZ)]),
             "lbm_create": (ctypes.c_int, [DP, ctypes.c_int, P, D, ctypes.POINTER(D), ctypes.POINTER(P)]),
             "lbm_destroy": (ctypes.c_int, [P]),
             "lbm_last_error": (ctypes.c_char_p, [P]),
@@ -153,9 +154,16 @@ def make_domain(shape, bc=("periodic",) * 6, u_bc=None, rho_bc=None, storage="f3
     return d
 
 
-def workspace_bytes(domain: Domain, q: int) -> int:
+def workspace_bytes(domain: Domain, q: int, flags: Optional[np.ndarray] = None) -> int:
+    """Workspace bytes of a context; with `flags` (uint8 per cell) sized for
+    those solids (sparse addressing stores fluid cells only)."""
     out = ctypes.c_size_t(0)
-    _check(lib().lbm_workspace_bytes(ctypes.byref(domain), int(q), ctypes.byref(out)))
+    if flags is None:
+        _check(lib().lbm_workspace_bytes(ctypes.byref(domain), int(q), ctypes.byref(out)))
+    else:
+        f = np.ascontiguousarray(flags, dtype=np.uint8).reshape(-1)
+        _check(lib().lbm_workspace_bytes_flags(ctypes.byref(domain), int(q), f.ctypes.data_as(ctypes.c_void_p),
+                                               ctypes.byref(out)))
     return int(out.value)
 
 
@@ -172,7 +180,12 @@ class Lattice:
         self.n = self.shape[0] * self.shape[1] * self.shape[2]
         self.domain = make_domain(shape, bc, u_bc, rho_bc, storage, closure, solid is not None, magic, cs,
                                   collision, mrt_rates, streaming)
-        nbytes = workspace_bytes(self.domain, self.q)
+        flags = None
+        if solid is not None:
+            self._flags = np.ascontiguousarray(solid, dtype=np.uint8).reshape(-1)
+            assert self._flags.size == self.n
+            flags = self._flags.ctypes.data_as(ctypes.c_void_p)
+        nbytes = workspace_bytes(self.domain, self.q, None if solid is None else self._flags)
         # torch's caching allocator returns 512-byte aligned blocks
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.domain.workspace = self.workspace.data_ptr()
@@ -180,11 +193,6 @@ class Lattice:
         self.stream = torch.cuda.current_stream(self.device)
         self.domain.stream = self.stream.cuda_stream
         F = (ctypes.c_double * 3)(*[float(v) for v in force])
-        flags = None
-        if solid is not None:
-            self._flags = np.ascontiguousarray(solid, dtype=np.uint8).reshape(-1)
-            assert self._flags.size == self.n
-            flags = self._flags.ctypes.data_as(ctypes.c_void_p)
         h = ctypes.c_void_p(0)
         _check(lib().lbm_create(ctypes.byref(self.domain), self.q, flags, float(tau), F, ctypes.byref(h)))
         self._h = h

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2305_09910_amd import lbm
@@ -86,6 +87,26 @@ def test_et_workspace_holds_the_ghost_layers(L):
     assert d_rejects(L, lbm.make_domain((8, 8, 8), streaming=5))
 
 
+def test_sparse_workspace_is_sized_by_the_fluid_cells(L):
+    """Sparse addressing: populations, fluid list and neighbour table scale
+    with the fluid cells (chunks of 64), the fluid map with all cells."""
+    nx, ny, nz = 64, 32, 16
+    n = nx * ny * nz
+    solid = np.zeros(n, np.uint8)
+    solid[: 3 * n // 4] = 1  # a quarter of the cells stay fluid
+    nf = n - int(solid.sum())
+    dense = lbm.workspace_bytes(lbm.make_domain((nx, ny, nz), use_flags=True), 19, solid)
+    sp_dom = lbm.make_domain((nx, ny, nz), use_flags=True, streaming="sparse")
+    bound = lbm.workspace_bytes(sp_dom, 19)
+    exact = lbm.workspace_bytes(sp_dom, 19, solid)
+    # q populations + 1 fluid-list word + (q - 1) table words per fluid cell, 4 map bytes per cell
+    per_fluid = 19 * 4 + 4 + 18 * 4
+    assert bound - exact == pytest.approx(per_fluid * (n - nf), abs=4 * 256)
+    assert exact < dense
+    # without flags the sparse bound equals the flag-free count
+    assert lbm.workspace_bytes(sp_dom, 19) == lbm.workspace_bytes(sp_dom, 19, np.zeros(n, np.uint8))
+
+
 def d_rejects(L, d):
     out = ctypes.c_size_t(0)
     return L.lbm_workspace_bytes(ctypes.byref(d), 19, ctypes.byref(out)) == lbm.LBM_EINVAL
@@ -104,7 +125,8 @@ def _create(L, d, q=19, tau=0.6, flags=None):
     return rc, h
 
 
-@pytest.mark.parametrize("case", ["tau", "pairing", "bcenum", "null_ws", "small_ws", "align", "flags", "et_mlp"])
+@pytest.mark.parametrize("case", ["tau", "pairing", "bcenum", "null_ws", "small_ws", "align", "flags", "et_mlp",
+                                  "sparse_mlp", "sparse_small_ws"])
 def test_create_rejects_before_device(L, case):
     d = lbm.make_domain((8, 8, 8))
     need = lbm.workspace_bytes(d, 19)
@@ -131,6 +153,19 @@ def test_create_rejects_before_device(L, case):
         d.streaming = lbm.STREAMING["et"]
         d.closure = lbm.CLOSURE["mlp"]
         d.workspace_bytes = lbm.workspace_bytes(d, 19)
+    elif case == "sparse_mlp":
+        d.streaming = lbm.STREAMING["sparse"]
+        d.closure = lbm.CLOSURE["mlp"]
+        d.workspace_bytes = lbm.workspace_bytes(d, 19)
+    elif case == "sparse_small_ws":
+        # sized for half of the cells solid, created with all fluid
+        d.streaming = lbm.STREAMING["sparse"]
+        d.use_flags = 1
+        half = np.zeros(512, np.uint8)
+        half[:256] = 1
+        d.workspace_bytes = lbm.workspace_bytes(d, 19, half)
+        buf = (ctypes.c_uint8 * 512)()
+        flags = ctypes.cast(buf, ctypes.c_void_p)
     rc, h = _create(L, d, tau=tau, flags=flags)
     assert rc == lbm.LBM_EINVAL and not h.value
     assert len(L.lbm_last_error(None)) > 0

@@ -17,6 +17,8 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
+# in-place schemes: AA pattern, Esoteric Twist, AA over the fluid cells only (sparse addressing)
+SCHEMES = ["aa", "et", "sparse"]
 MRT27_RATES = (1.6, 1.75, 1.55, 1.65, 1.7)  # stable ghost rates of the D3Q27 tensor-product basis
 
 
@@ -67,7 +69,7 @@ def max_rel(g_pdfs, o_pdfs, solid=None):
 # ---------------------------------------------------------------------------
 # FP32 parity
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 def test_taylor_green_32cubed_1000_steps(streaming):
     """Taylor-Green vortex, D3Q19 TRT, 32^3 periodic, nu = 0.01, u0 = 0.05."""
     n = 32
@@ -98,7 +100,7 @@ def test_taylor_green_32cubed_1000_steps(streaming):
     assert abs(amp / expect - 1) < 0.01
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 @pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("nsteps", [1, 2, 3, 10, 11])
 def test_parity_aware_state_after_odd_and_even_steps(q, nsteps, streaming):
@@ -127,7 +129,7 @@ def test_parity_aware_state_after_odd_and_even_steps(q, nsteps, streaming):
     assert np.array_equal(gat, full)
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 @pytest.mark.parametrize("q", [19, 27])
 def test_every_boundary_kind_on_every_axis(q, streaming):
     """No-slip, velocity and pressure faces on all three axes with solids and
@@ -154,7 +156,7 @@ def test_every_boundary_kind_on_every_axis(q, streaming):
     assert err <= TOL32
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 def test_channel_1000_steps(streaming):
     """Channel shape (walls on y, periodic x and z, force in x, parabola plus
     5% noise), a 64x32x32 copy of the 256x128x128 channel, 1000 steps."""
@@ -176,7 +178,7 @@ def test_channel_1000_steps(streaming):
     assert abs(mg - mo) / mo < 1e-7
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 def test_obstacle_d3q27_200_steps(streaming):
     """D3Q27 obstacle flow, the 128^3 copy of the 384^3 workload: velocity
     inflow 0.04 at -x, pressure outflow at +x, periodic y/z, random spheres
@@ -198,7 +200,7 @@ def test_obstacle_d3q27_200_steps(streaming):
     assert err <= TOL32
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 @pytest.mark.parametrize("shape,walls", [
     ((1, 9, 7), ("periodic", "periodic", "noslip", "noslip", "velocity", "pressure")),  # one cell along periodic x
     ((11, 1, 6), ("pressure", "velocity", "noslip", "noslip", "periodic", "periodic")),  # one cell between two walls
@@ -229,7 +231,7 @@ def test_degenerate_and_ragged_shapes(q, shape, walls, streaming):
         assert max_rel(g.get_pdfs(), o.get_pdfs()) <= 1e-6, n
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 def test_obstacle_flow_steady_mass_flux(streaming):
     """Duct past a sphere (velocity inlet, pressure outlet), D3Q27, 4000
     steps: the GPU state matches the oracle, and at steady state the mass
@@ -252,7 +254,7 @@ def test_obstacle_flow_steady_mass_flux(streaming):
     assert np.abs(flux / flux.mean() - 1).max() < 1e-3
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 @pytest.mark.parametrize("q", [19, 27])
 def test_smagorinsky_closure(q, streaming):
     nx, ny, nz = 32, 16, 16
@@ -289,7 +291,7 @@ def test_mrt_channel(q, closure):
     assert err <= TOL32
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 @pytest.mark.parametrize("q", [19, 27])
 def test_mrt_every_boundary_kind_and_solids(q, streaming):
     shape = (20, 14, 10)
@@ -324,7 +326,7 @@ def test_mrt_rejects_mlp_and_bad_rates():
 # ---------------------------------------------------------------------------
 # state readers and robustness
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 def test_moments_and_set_pdfs_roundtrip(streaming):
     shape = (24, 10, 6)
     g, o = pair(shape, force=(1e-4, 0, 0), bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"),
@@ -366,7 +368,7 @@ def test_low_precision_storage_rounding(storage, tdtype):
     assert np.allclose(got, expect, rtol=0, atol=1e-17)
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", SCHEMES)
 def test_run_twice_bit_identical_and_checkpoint_resume(streaming):
     shape = (32, 16, 8)
     kw = dict(tau=0.55, force=(1e-5, 0, 0), bc=("periodic", "periodic", "noslip", "noslip", "periodic", "periodic"),
