@@ -34,6 +34,14 @@ def _case(name):
         F = 8 * (1 / 300) * 0.05 / ny ** 2
         rho, u = inputs.channel(nx, ny, nz, 0.05, 0.05, seed=1234)
         return dict(shape=(nx, ny, nz), q=19, tau=0.51, force=(F, 0, 0), bc=WALLS_Y, solid=None, u_bc=None), rho, u
+    if name == "porous_256":
+        # the porous-medium benchmark: 70% solid, periodic, force-driven
+        n = 256
+        solid = inputs.porous(n, n, n, solid_fraction=0.7, rmin=3.0, rmax=8.0, seed=77)
+        rho, u = inputs.uniform_flow(n, n, n, (0.0, 0, 0))
+        u += inputs.perturbation(u.shape, 0.002, seed=98) * (solid == 0)
+        return dict(shape=(n, n, n), q=19, tau=0.6, force=(1e-5, 0, 0), bc=("periodic",) * 6, solid=solid,
+                    u_bc=None), rho, u
     n = 384
     solid, _ = inputs.spheres(n, n, n, fill=0.10, x_margin=32, seed=2024)
     uw = np.zeros((6, 3))
@@ -130,10 +138,15 @@ def _timing_network(seed=9):
     ("channel_512x256x256", "f32", "et", "none"),
     ("channel_512x256x256", "f16", "et", "none"),
     ("obstacles_384_d3q27", "f32", "et", "none"),
+    ("porous_256", "f32", "aa", "none"),
+    ("porous_256", "f32", "sparse", "none"),
+    ("porous_256", "f16", "sparse", "none"),
+    ("obstacles_384_d3q27", "f32", "sparse", "none"),
 ])
-def test_closures_and_esoteric_twist_sampled_against_probe(name, storage, streaming, closure):
-    """The closure forms and the Esoteric Twist forms at their benchmark
-    shapes: two steps, sampled cells against the oracle's probe."""
+def test_closure_et_and_sparse_forms_sampled_against_probe(name, storage, streaming, closure):
+    """The closure forms, the Esoteric Twist forms and the sparse-addressing
+    forms at their benchmark shapes: two steps, sampled cells against the
+    oracle's probe."""
     from paper_2305_09910_amd import lbm
     cfg, rho, u = _case(name)
     print(f"[case] {name} storage={storage} streaming={streaming} closure={closure}", flush=True)
