@@ -41,10 +41,6 @@ struct LatticeArgs {
     int sx, sy;              // cells per stored row and rows per stored plane: nx, ny, or one more
                              // for the ghost layer of the Esoteric Twist on a non-periodic + face
     int et;                  // streaming scheme: 0 AA pattern, 1 Esoteric Twist
-    int sp;                  // sparse addressing: the AA pattern over the fluid cells only
-    uint32_t nf;             // fluid cells (sparse addressing)
-    const int32_t *fmap;     // [n] fluid index of each cell, -1 for solid cells (sparse addressing)
-    const uint32_t *nbt;     // neighbour table [chunk][q - 1][64] (sparse addressing)
     int per[3];              // axis periodic?
     int bc[6];               // face kinds
     int any_vp;              // any velocity / pressure face
@@ -59,6 +55,16 @@ struct LatticeArgs {
     unsigned long long *fallbacks;  // MLP fallback counter (device) or nullptr
 };
 
+// Sparse addressing (the AA pattern over the fluid cells only), passed as an
+// argument of its own to the kernels that use it: the dense step kernels keep
+// exactly their argument block (its layout moves their compiled code).
+struct SparseArgs {
+    int on;                  // sparse addressing in use
+    uint32_t nf;             // fluid cells
+    const int32_t *fmap;     // [n] fluid index of each cell, -1 for solid cells
+    const uint32_t *nbt;     // neighbour table [chunk][q - 1][64]
+};
+
 struct Launch {
     dim3 grid, block;
 };
@@ -71,19 +77,24 @@ hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int coll, in
 hipError_t launch_step_et(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
 // sparse addressing (lbm_sparse.hip): neighbour table from the fluid map and
 // the fluid cells' linear indices, and the step; no learned closure
-hipError_t launch_build_sparse_table(const LatticeArgs &a, int q, const uint32_t *fcell, uint32_t *table,
-                                     hipStream_t s);
-hipError_t launch_step_sparse(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
-hipError_t launch_init_eq(const LatticeArgs &a, int q, int st, const double *rho, const double *u, hipStream_t s);
-hipError_t launch_set_pdfs(const LatticeArgs &a, int q, int st, const double *f, hipStream_t s);
-hipError_t launch_get_pdfs(const LatticeArgs &a, int q, int st, int odd, double *f, hipStream_t s);
-hipError_t launch_gather(const LatticeArgs &a, int q, int st, int odd, const int64_t *cells, int64_t ncell,
-                         double *out, hipStream_t s);
-hipError_t launch_moments(const LatticeArgs &a, int q, int st, int odd, float *rho, float *u, hipStream_t s);
+hipError_t launch_build_sparse_table(const LatticeArgs &a, const SparseArgs &sp, int q, const uint32_t *fcell,
+                                     uint32_t *table, hipStream_t s);
+hipError_t launch_step_sparse(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int cl, int coll, int odd,
+                              hipStream_t s);
+// State kernels (any scheme).
+hipError_t launch_init_eq(const LatticeArgs &a, const SparseArgs &sp, int q, int st, const double *rho,
+                          const double *u, hipStream_t s);
+hipError_t launch_set_pdfs(const LatticeArgs &a, const SparseArgs &sp, int q, int st, const double *f, hipStream_t s);
+hipError_t launch_get_pdfs(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int odd, double *f,
+                           hipStream_t s);
+hipError_t launch_gather(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int odd, const int64_t *cells,
+                         int64_t ncell, double *out, hipStream_t s);
+hipError_t launch_moments(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int odd, float *rho, float *u,
+                          hipStream_t s);
 // totals: partial[nblk][5] doubles then final[5] = {sum drho, jx, jy, jz, nonfinite-count}
 int totals_blocks();
-hipError_t launch_totals(const LatticeArgs &a, int q, int st, int odd, double *partial, double *final_out,
-                         hipStream_t s);
+hipError_t launch_totals(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int odd, double *partial,
+                         double *final_out, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 // operand table of the closure network (63 x 64 words) from its parameters
 hipError_t launch_build_mlp_table(const float *params, uint32_t *table, hipStream_t s);

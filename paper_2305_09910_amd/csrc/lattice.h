@@ -260,26 +260,6 @@ __device__ inline void load_canonical(const LatticeArgs &a, const Geom &g, uint3
 {
     using S = Store<ST>;
     const typename S::T *A = (const typename S::T *)a.pdf;
-    if (a.sp) {
-        // sparse addressing (fluid cells only): the AA pattern over the
-        // fluid index; after an odd number of steps f_i sits in slot
-        // opposite(i) of the neighbour x - c_i, or in the cell's own slot i
-        // when that link is cut
-        const int32_t kf = a.fmap[g.c];
-        if (kf < 0) {  // solid cell: nothing stored
-#pragma unroll
-            for (int i = 0; i < Q; ++i) d[i] = 0.f;
-            return;
-        }
-        const uint32_t k = (uint32_t)kf;
-        d[0] = S::ld(A + sp_index<Q>(k, 0));
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const uint32_t t = odd ? a.nbt[sp_table<Q>(k, opp(i))] : NB_FACE0;
-            d[i] = S::ld(A + (t >= NB_FACE0 ? sp_index<Q>(k, i) : sp_index<Q>(t, opp(i))));
-        }
-        return;
-    }
     if (a.et) {
         // Esoteric Twist: f_i(x) sits at x + max(-c_i, 0) in slot i after an
         // even number of steps, slot opposite(i) after an odd number, cut
@@ -565,12 +545,42 @@ __device__ inline void mrt_collide(const LatticeArgs &a, float (&d)[Q], float dr
     });
 }
 
+// Canonical read for the state kernels, any scheme.  With sparse addressing
+// (fluid cells only, the AA pattern over the fluid index) f_i sits after an
+// odd number of steps in slot opposite(i) of the neighbour x - c_i, or in the
+// cell's own slot i when that link is cut; solid cells read as zero
+// deviations.
+template <int Q, int ST>
+__device__ inline void load_state(const LatticeArgs &a, const SparseArgs &sp, const Geom &g, uint32_t m, int odd,
+                                  float (&d)[Q])
+{
+    if (!sp.on) {
+        load_canonical<Q, ST>(a, g, m, odd, d);
+        return;
+    }
+    using S = Store<ST>;
+    const typename S::T *A = (const typename S::T *)a.pdf;
+    const int32_t kf = sp.fmap[g.c];
+    if (kf < 0) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = 0.f;
+        return;
+    }
+    const uint32_t k = (uint32_t)kf;
+    d[0] = S::ld(A + sp_index<Q>(k, 0));
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const uint32_t t = odd ? sp.nbt[sp_table<Q>(k, opp(i))] : NB_FACE0;
+        d[i] = S::ld(A + (t >= NB_FACE0 ? sp_index<Q>(k, i) : sp_index<Q>(t, opp(i))));
+    }
+}
+
 // Storage index of f_i(x) after zero steps (any scheme; with sparse
 // addressing only for fluid cells).
 template <int Q>
-__device__ inline uint64_t index_t0(const LatticeArgs &a, const Geom &g, int i)
+__device__ inline uint64_t index_t0(const LatticeArgs &a, const SparseArgs &sp, const Geom &g, int i)
 {
-    if (a.sp) return sp_index<Q>((uint32_t)a.fmap[g.c], i);
+    if (sp.on) return sp_index<Q>((uint32_t)sp.fmap[g.c], i);
     if (a.et) return et_index<Q>(a, g, i, cdir(i, 0) < 0, cdir(i, 1) < 0, cdir(i, 2) < 0);
     return pidx<Q>(a, i, g.row, g.x);
 }

@@ -29,6 +29,7 @@ using namespace lbm;
 
 struct lbm_ctx {
     LatticeArgs a;
+    SparseArgs sp;
     int q, st, cl, coll;
     int64_t time;
     hipStream_t stream;
@@ -251,10 +252,10 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     a.sx = L.sx;
     a.sy = L.sy;
     a.et = d->streaming == LBM_STREAM_ET;
-    a.sp = sp;
-    a.nf = (uint32_t)nf;
-    a.fmap = sp ? (const int32_t *)(c->ws + L.fmap) : nullptr;
-    a.nbt = sp ? (const uint32_t *)(c->ws + L.nbt) : nullptr;
+    c->sp.on = sp;
+    c->sp.nf = (uint32_t)nf;
+    c->sp.fmap = sp ? (const int32_t *)(c->ws + L.fmap) : nullptr;
+    c->sp.nbt = sp ? (const uint32_t *)(c->ws + L.nbt) : nullptr;
     for (int k = 0; k < 3; ++k) a.per[k] = d->bc[2 * k] == LBM_BC_PERIODIC;
     a.any_vp = 0;
     for (int f = 0; f < 6; ++f) {
@@ -311,7 +312,7 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
         if (e == hipSuccess && nf > 0)
             e = hipMemcpyAsync(c->ws + L.fcell, fcell, (size_t)4 * nf, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess)
-            e = launch_build_sparse_table(a, stencil, (const uint32_t *)(c->ws + L.fcell), (uint32_t *)(c->ws + L.nbt),
+            e = launch_build_sparse_table(a, c->sp, stencil, (const uint32_t *)(c->ws + L.fcell), (uint32_t *)(c->ws + L.nbt),
                                           c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // before the host arrays go
         delete[] fmap;
@@ -339,7 +340,7 @@ int lbm_init_equilibrium(lbm_ctx *c, const double *rho_dev, const double *u_dev)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
     if (!rho_dev || !u_dev) return fail(c, LBM_EINVAL, "rho/u is NULL");
-    HIPCHECK(c, launch_init_eq(c->a, c->q, c->st, rho_dev, u_dev, c->stream), "init_equilibrium");
+    HIPCHECK(c, launch_init_eq(c->a, c->sp, c->q, c->st, rho_dev, u_dev, c->stream), "init_equilibrium");
     c->time = 0;
     return LBM_OK;
 }
@@ -348,7 +349,7 @@ int lbm_set_pdfs(lbm_ctx *c, const double *f_dev)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
     if (!f_dev) return fail(c, LBM_EINVAL, "f is NULL");
-    HIPCHECK(c, launch_set_pdfs(c->a, c->q, c->st, f_dev, c->stream), "set_pdfs");
+    HIPCHECK(c, launch_set_pdfs(c->a, c->sp, c->q, c->st, f_dev, c->stream), "set_pdfs");
     c->time = 0;
     return LBM_OK;
 }
@@ -357,7 +358,7 @@ int lbm_get_pdfs(lbm_ctx *c, double *f_dev)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
     if (!f_dev) return fail(c, LBM_EINVAL, "f is NULL");
-    HIPCHECK(c, launch_get_pdfs(c->a, c->q, c->st, (int)(c->time & 1), f_dev, c->stream), "get_pdfs");
+    HIPCHECK(c, launch_get_pdfs(c->a, c->sp, c->q, c->st, (int)(c->time & 1), f_dev, c->stream), "get_pdfs");
     return LBM_OK;
 }
 
@@ -366,7 +367,7 @@ int lbm_gather_pdfs(lbm_ctx *c, const int64_t *cells_dev, int64_t n, double *out
     if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
     if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
     if (n > 0 && (!cells_dev || !out_dev)) return fail(c, LBM_EINVAL, "cells/out is NULL");
-    HIPCHECK(c, launch_gather(c->a, c->q, c->st, (int)(c->time & 1), cells_dev, n, out_dev, c->stream), "gather");
+    HIPCHECK(c, launch_gather(c->a, c->sp, c->q, c->st, (int)(c->time & 1), cells_dev, n, out_dev, c->stream), "gather");
     return LBM_OK;
 }
 
@@ -378,7 +379,7 @@ int lbm_step(lbm_ctx *c, int64_t n)
         return fail(c, LBM_ESTATE, "MLP closure selected but lbm_set_closure_weights was not called");
     for (int64_t k = 0; k < n; ++k) {
         const int odd = (int)(c->time & 1);
-        hipError_t e = c->a.sp   ? launch_step_sparse(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream)
+        hipError_t e = c->sp.on  ? launch_step_sparse(c->a, c->sp, c->q, c->st, c->cl, c->coll, odd, c->stream)
                        : c->a.et ? launch_step_et(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream)
                                  : launch_step(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "stream_collide launch");
@@ -393,7 +394,7 @@ int lbm_moments(lbm_ctx *c, float *rho_dev, float *u_dev)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
     if (!rho_dev || !u_dev) return fail(c, LBM_EINVAL, "rho/u is NULL");
-    HIPCHECK(c, launch_moments(c->a, c->q, c->st, (int)(c->time & 1), rho_dev, u_dev, c->stream), "moments");
+    HIPCHECK(c, launch_moments(c->a, c->sp, c->q, c->st, (int)(c->time & 1), rho_dev, u_dev, c->stream), "moments");
     return LBM_OK;
 }
 
@@ -401,7 +402,7 @@ int lbm_totals(lbm_ctx *c, double *mass, double mom[3])
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
     if (!mass || !mom) return fail(c, LBM_EINVAL, "mass/mom is NULL");
-    HIPCHECK(c, launch_totals(c->a, c->q, c->st, (int)(c->time & 1), c->partial, c->final_out, c->stream),
+    HIPCHECK(c, launch_totals(c->a, c->sp, c->q, c->st, (int)(c->time & 1), c->partial, c->final_out, c->stream),
              "totals");
     double h[5];
     HIPCHECK(c, hipMemcpyAsync(h, c->final_out, sizeof h, hipMemcpyDeviceToHost, c->stream), "totals copy");

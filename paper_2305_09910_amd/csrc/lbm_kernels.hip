@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_build_mask(LatticeArgs a, co
 }
 
 template <int Q, int ST>
-__global__ void __launch_bounds__(LBM_LB_THREADS) k_init_eq(LatticeArgs a, const double *rho, const double *u)
+__global__ void __launch_bounds__(LBM_LB_THREADS) k_init_eq(LatticeArgs a, SparseArgs sp, const double *rho, const double *u)
 {
     using S = Store<ST>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_init_eq(LatticeArgs a, const
     if (x >= a.nx || y >= a.ny) return;
     const Geom g = make_geom(a, x, y, z);
     const bool solid = a.mask && (a.mask[g.c] & SELF_SOLID);
-    if (a.sp && a.fmap[g.c] < 0) return;  // sparse addressing stores fluid cells only
+    if (sp.on && sp.fmap[g.c] < 0) return;  // sparse addressing stores fluid cells only
     const double r = rho[g.c], ux = u[g.c], uy = u[(uint64_t)a.n + g.c], uz = u[2 * (uint64_t)a.n + g.c];
     const double usq = ux * ux + uy * uy + uz * uz;
     typename S::T *A = (typename S::T *)a.pdf;
@@ -205,12 +205,12 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_init_eq(LatticeArgs a, const
     for (int i = 0; i < Q; ++i) {
         const double cu = cdir(i, 0) * ux + cdir(i, 1) * uy + cdir(i, 2) * uz;
         const double dev = wgt<Q>(i) * ((r - 1.0) + r * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
-        A[index_t0<Q>(a, g, i)] = S::cvt(solid ? 0.f : (float)dev);
+        A[index_t0<Q>(a, sp, g, i)] = S::cvt(solid ? 0.f : (float)dev);
     }
 }
 
 template <int Q, int ST>
-__global__ void __launch_bounds__(LBM_LB_THREADS) k_set_pdfs(LatticeArgs a, const double *f)
+__global__ void __launch_bounds__(LBM_LB_THREADS) k_set_pdfs(LatticeArgs a, SparseArgs sp, const double *f)
 {
     using S = Store<ST>;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -218,16 +218,16 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_set_pdfs(LatticeArgs a, cons
     const int z = blockIdx.z;
     if (x >= a.nx || y >= a.ny) return;
     const Geom g = make_geom(a, x, y, z);
-    if (a.sp && a.fmap[g.c] < 0) return;  // sparse addressing stores fluid cells only
+    if (sp.on && sp.fmap[g.c] < 0) return;  // sparse addressing stores fluid cells only
     typename S::T *A = (typename S::T *)a.pdf;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        A[index_t0<Q>(a, g, i)] = S::cvt((float)(f[(uint64_t)i * a.n + g.c] - wgt<Q>(i)));
+        A[index_t0<Q>(a, sp, g, i)] = S::cvt((float)(f[(uint64_t)i * a.n + g.c] - wgt<Q>(i)));
     }
 }
 
 template <int Q, int ST>
-__global__ void __launch_bounds__(LBM_LB_THREADS) k_get_pdfs(LatticeArgs a, int odd, double *f)
+__global__ void __launch_bounds__(LBM_LB_THREADS) k_get_pdfs(LatticeArgs a, SparseArgs sp, int odd, double *f)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -240,14 +240,14 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_get_pdfs(LatticeArgs a, int 
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] = 0.f;
     } else {
-        load_canonical<Q, ST>(a, g, m, odd, d);
+        load_state<Q, ST>(a, sp, g, m, odd, d);
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[(uint64_t)i * a.n + g.c] = wgt<Q>(i) + (double)d[i];
 }
 
 template <int Q, int ST>
-__global__ void __launch_bounds__(256) k_gather(LatticeArgs a, int odd, const int64_t *cells, int64_t ncell,
+__global__ void __launch_bounds__(256) k_gather(LatticeArgs a, SparseArgs sp, int odd, const int64_t *cells, int64_t ncell,
                                                 double *out)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -266,14 +266,14 @@ __global__ void __launch_bounds__(256) k_gather(LatticeArgs a, int odd, const in
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] = 0.f;
     } else {
-        load_canonical<Q, ST>(a, g, m, odd, d);
+        load_state<Q, ST>(a, sp, g, m, odd, d);
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) out[r * Q + i] = wgt<Q>(i) + (double)d[i];
 }
 
 template <int Q, int ST>
-__global__ void __launch_bounds__(LBM_LB_THREADS) k_moments(LatticeArgs a, int odd, float *rho, float *u)
+__global__ void __launch_bounds__(LBM_LB_THREADS) k_moments(LatticeArgs a, SparseArgs sp, int odd, float *rho, float *u)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -287,7 +287,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_moments(LatticeArgs a, int o
         return;
     }
     float d[Q];
-    load_canonical<Q, ST>(a, g, m, odd, d);
+    load_state<Q, ST>(a, sp, g, m, odd, d);
     float drho;
     const Macro M = moments<Q>(a, d, drho);
     rho[g.c] = M.rho;
@@ -309,7 +309,7 @@ __device__ inline double wave_sum(double v)
 }
 
 template <int Q, int ST>
-__global__ void __launch_bounds__(256) k_totals(LatticeArgs a, int odd, double *partial)
+__global__ void __launch_bounds__(256) k_totals(LatticeArgs a, SparseArgs sp, int odd, double *partial)
 {
     double acc[5] = {0, 0, 0, 0, 0};
     const uint32_t per_block = (a.n + TOT_BLOCKS - 1) / TOT_BLOCKS;
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(256) k_totals(LatticeArgs a, int odd, double *
         const uint32_t m = a.mask ? a.mask[g.c] : 0u;
         if (m & SELF_SOLID) continue;
         float d[Q];
-        load_canonical<Q, ST>(a, g, m, odd, d);
+        load_state<Q, ST>(a, sp, g, m, odd, d);
         float s = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
@@ -462,60 +462,63 @@ hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int coll, in
     return dispatch(q, st, [&](auto Q, auto ST) { return step_q_st<Q.value, ST.value>(a, cl, coll, odd, s); });
 }
 
-hipError_t launch_init_eq(const LatticeArgs &a, int q, int st, const double *rho, const double *u, hipStream_t s)
+hipError_t launch_init_eq(const LatticeArgs &a, const SparseArgs &sp, int q, int st, const double *rho,
+                          const double *u, hipStream_t s)
 {
     const Launch L = lattice_launch(a);
     return dispatch(q, st, [&](auto Q, auto ST) {
-        k_init_eq<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, rho, u);
+        k_init_eq<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, sp, rho, u);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_set_pdfs(const LatticeArgs &a, int q, int st, const double *f, hipStream_t s)
+hipError_t launch_set_pdfs(const LatticeArgs &a, const SparseArgs &sp, int q, int st, const double *f, hipStream_t s)
 {
     const Launch L = lattice_launch(a);
     return dispatch(q, st, [&](auto Q, auto ST) {
-        k_set_pdfs<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, f);
+        k_set_pdfs<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, sp, f);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_get_pdfs(const LatticeArgs &a, int q, int st, int odd, double *f, hipStream_t s)
+hipError_t launch_get_pdfs(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int odd, double *f,
+                           hipStream_t s)
 {
     const Launch L = lattice_launch(a);
     return dispatch(q, st, [&](auto Q, auto ST) {
-        k_get_pdfs<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, odd, f);
+        k_get_pdfs<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, sp, odd, f);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_gather(const LatticeArgs &a, int q, int st, int odd, const int64_t *cells, int64_t ncell,
-                         double *out, hipStream_t s)
+hipError_t launch_gather(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int odd, const int64_t *cells,
+                         int64_t ncell, double *out, hipStream_t s)
 {
     if (ncell <= 0) return hipSuccess;
     const dim3 grid((unsigned)((ncell + 255) / 256)), block(256);
     return dispatch(q, st, [&](auto Q, auto ST) {
-        k_gather<Q.value, ST.value><<<grid, block, 0, s>>>(a, odd, cells, ncell, out);
+        k_gather<Q.value, ST.value><<<grid, block, 0, s>>>(a, sp, odd, cells, ncell, out);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_moments(const LatticeArgs &a, int q, int st, int odd, float *rho, float *u, hipStream_t s)
+hipError_t launch_moments(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int odd, float *rho, float *u,
+                          hipStream_t s)
 {
     const Launch L = lattice_launch(a);
     return dispatch(q, st, [&](auto Q, auto ST) {
-        k_moments<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, odd, rho, u);
+        k_moments<Q.value, ST.value><<<L.grid, L.block, 0, s>>>(a, sp, odd, rho, u);
         return hipGetLastError();
     });
 }
 
 int totals_blocks() { return TOT_BLOCKS; }
 
-hipError_t launch_totals(const LatticeArgs &a, int q, int st, int odd, double *partial, double *final_out,
-                         hipStream_t s)
+hipError_t launch_totals(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int odd, double *partial,
+                         double *final_out, hipStream_t s)
 {
     hipError_t e = dispatch(q, st, [&](auto Q, auto ST) {
-        k_totals<Q.value, ST.value><<<TOT_BLOCKS, 256, 0, s>>>(a, odd, partial);
+        k_totals<Q.value, ST.value><<<TOT_BLOCKS, 256, 0, s>>>(a, sp, odd, partial);
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;

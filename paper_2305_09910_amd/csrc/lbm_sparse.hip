@@ -26,11 +26,11 @@
 namespace lbm {
 
 template <int Q, int ST, int CL, int COLL>
-__global__ void __launch_bounds__(256) k_stream_collide_sparse(LatticeArgs a, int odd)
+__global__ void __launch_bounds__(256) k_stream_collide_sparse(LatticeArgs a, SparseArgs sp, int odd)
 {
     using S = Store<ST>;
     const uint32_t k = blockIdx.x * 256u + threadIdx.x;
-    if (k >= a.nf) return;
+    if (k >= sp.nf) return;
     typename S::T *A = (typename S::T *)a.pdf;
     // neighbour table: all q - 1 entries on the odd step (each serves one
     // read and one write), only with velocity/pressure faces on the even one
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) k_stream_collide_sparse(LatticeArgs a, in
     const bool need = odd || a.any_vp;
     for_dirs<1, Q>([&](auto J) {
         constexpr int j = decltype(J)::value;
-        t[j] = need ? __builtin_nontemporal_load(a.nbt + sp_table<Q>(k, j)) : NB_SOLID;
+        t[j] = need ? __builtin_nontemporal_load(sp.nbt + sp_table<Q>(k, j)) : NB_SOLID;
     });
     float d[Q];
     for_dirs<0, Q>([&](auto I) {
@@ -82,10 +82,10 @@ __global__ void __launch_bounds__(256) k_stream_collide_sparse(LatticeArgs a, in
 // One thread per fluid cell: its neighbour along each c_j (periodic wrap),
 // or the code of the face or solid that cuts the link.
 template <int Q>
-__global__ void __launch_bounds__(256) k_build_sparse_table(LatticeArgs a, const uint32_t *fcell, uint32_t *T)
+__global__ void __launch_bounds__(256) k_build_sparse_table(LatticeArgs a, SparseArgs sp, const uint32_t *fcell, uint32_t *T)
 {
     const uint32_t k = blockIdx.x * 256u + threadIdx.x;
-    if (k >= a.nf) return;
+    if (k >= sp.nf) return;
     const uint32_t c = fcell[k];
     const int x = (int)(c % (uint32_t)a.nx), y = (int)((c / (uint32_t)a.nx) % (uint32_t)a.ny);
     const int z = (int)(c / ((uint32_t)a.nx * (uint32_t)a.ny));
@@ -97,45 +97,46 @@ __global__ void __launch_bounds__(256) k_build_sparse_table(LatticeArgs a, const
         if (face_cut(g, dx, dy, dz)) {
             e = NB_FACE0 + (uint32_t)deciding_face(a, g, dx, dy, dz);
         } else {
-            const int32_t f = a.fmap[nbr(a, g, dx, dy, dz)];
+            const int32_t f = sp.fmap[nbr(a, g, dx, dy, dz)];
             e = f < 0 ? NB_SOLID : (uint32_t)f;
         }
         T[sp_table<Q>(k, j)] = e;
     }
 }
 
-hipError_t launch_build_sparse_table(const LatticeArgs &a, int q, const uint32_t *fcell, uint32_t *table,
-                                     hipStream_t s)
+hipError_t launch_build_sparse_table(const LatticeArgs &a, const SparseArgs &sp, int q, const uint32_t *fcell,
+                                     uint32_t *table, hipStream_t s)
 {
-    if (a.nf == 0) return hipSuccess;
-    const dim3 grid((a.nf + 255) / 256), block(256);
+    if (sp.nf == 0) return hipSuccess;
+    const dim3 grid((sp.nf + 255) / 256), block(256);
     if (q == 19)
-        k_build_sparse_table<19><<<grid, block, 0, s>>>(a, fcell, table);
+        k_build_sparse_table<19><<<grid, block, 0, s>>>(a, sp, fcell, table);
     else
-        k_build_sparse_table<27><<<grid, block, 0, s>>>(a, fcell, table);
+        k_build_sparse_table<27><<<grid, block, 0, s>>>(a, sp, fcell, table);
     return hipGetLastError();
 }
 
 template <int Q, int ST, int COLL>
-static void sparse_coll(const LatticeArgs &a, int cl, int odd, dim3 grid, hipStream_t s)
+static void sparse_coll(const LatticeArgs &a, const SparseArgs &sp, int cl, int odd, dim3 grid, hipStream_t s)
 {
     if (cl == CL_NONE)
-        k_stream_collide_sparse<Q, ST, CL_NONE, COLL><<<grid, 256, 0, s>>>(a, odd);
+        k_stream_collide_sparse<Q, ST, CL_NONE, COLL><<<grid, 256, 0, s>>>(a, sp, odd);
     else
-        k_stream_collide_sparse<Q, ST, CL_SMAG, COLL><<<grid, 256, 0, s>>>(a, odd);
+        k_stream_collide_sparse<Q, ST, CL_SMAG, COLL><<<grid, 256, 0, s>>>(a, sp, odd);
 }
 
-hipError_t launch_step_sparse(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s)
+hipError_t launch_step_sparse(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int cl, int coll, int odd,
+                              hipStream_t s)
 {
     if (cl == CL_MLP) return hipErrorInvalidValue;
-    if (a.nf == 0) return hipSuccess;
-    const dim3 grid((a.nf + 255) / 256);
+    if (sp.nf == 0) return hipSuccess;
+    const dim3 grid((sp.nf + 255) / 256);
     return dispatch(q, st, [&](auto Qc, auto STc) {
         constexpr int Q = decltype(Qc)::value, ST = decltype(STc)::value;
         if (coll == COLL_MRT)
-            sparse_coll<Q, ST, COLL_MRT>(a, cl, odd, grid, s);
+            sparse_coll<Q, ST, COLL_MRT>(a, sp, cl, odd, grid, s);
         else
-            sparse_coll<Q, ST, COLL_TRT>(a, cl, odd, grid, s);
+            sparse_coll<Q, ST, COLL_TRT>(a, sp, cl, odd, grid, s);
         return hipGetLastError();
     });
 }
