@@ -11,7 +11,9 @@
  *     and an optional per-cell solid mask,
  *   - one population set kept in place in HBM, streamed with the AA access
  *     pattern or with the Esoteric Twist the paper's LAGOON runs use
- *     (Section 5.2), structure of arrays within each row of cells: [z][y][q][x],
+ *     (Section 5.2), structure of arrays within each row of cells: [z][y][q][x];
+ *     or, for solid-heavy domains, the AA pattern over the fluid cells only
+ *     (sparse addressing),
  *   - optional LES closures (Smagorinsky, or a small learned MLP) that set a
  *     per-cell relaxation time.
  *
