@@ -168,7 +168,11 @@ def workspace_bytes(domain: Domain, q: int, flags: Optional[np.ndarray] = None) 
 
 
 class Lattice:
-    """One lattice on one GPU.  shape = (nx, ny, nz); fields are [nz, ny, nx]."""
+    """One lattice on one GPU.  shape = (nx, ny, nz); fields are [nz, ny, nx].
+
+    streaming: "aa" (AA pattern), "et" (Esoteric Twist) or "sparse" (the AA
+    pattern over the fluid cells only, for domains that `solid` fills to a
+    large part; the workspace is then sized by the fluid cells)."""
 
     def __init__(self, shape, q: int = 19, tau: float = 0.6, force=(0.0, 0.0, 0.0), bc=("periodic",) * 6,
                  u_bc=None, rho_bc=None, solid: Optional[np.ndarray] = None, storage="f32", closure="none",
