@@ -302,7 +302,7 @@ def main():
                     help="time only this form for --form-steps steps (for profiling); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the multi-GPU halo "
+        print(f"bench.py: the library runs on exactly one GPU (asked for {args.gpus}); the multi-GPU halo "
               f"exchange is a design only.", file=sys.stderr)
         sys.exit(2)
     import torch
