@@ -258,7 +258,7 @@ FORMS = ["channel_512x256x256_f32", "channel_512x256x256_f16", "channel_512x256x
          "channel_512x256x256_mlp_closure", "channel_512x256x256_mrt", "obstacles_384^3_d3q27_mrt",
          "channel_256x128x128_et", "channel_512x256x256_f32_et", "channel_512x256x256_f16_et",
          "obstacles_384^3_d3q27_et", "porous_256^3_d3q19_f32", "porous_256^3_d3q19_f32_sparse",
-         "porous_256^3_d3q19_f16", "porous_256^3_d3q19_f16_sparse"]
+         "porous_256^3_d3q19_f16", "porous_256^3_d3q19_f16_sparse", "channel_256x128x128_mlp_closure_et"]
 
 
 def form_cfg(key):
@@ -280,6 +280,7 @@ def form_cfg(key):
         "porous_256^3_d3q19_f32_sparse": lambda: porous_cfg(256, "f32", "sparse"),
         "porous_256^3_d3q19_f16": lambda: porous_cfg(256, "f16"),
         "porous_256^3_d3q19_f16_sparse": lambda: porous_cfg(256, "f16", "sparse"),
+        "channel_256x128x128_mlp_closure_et": lambda: dict(channel_cfg(256, 128, 128, "f32", "mlp"), streaming="et"),
     }[key]()
 
 

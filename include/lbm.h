@@ -98,7 +98,7 @@ enum { LBM_COLL_TRT = 0, LBM_COLL_MRT = 1 };
  *     writes at x + max(c_i, 0), the slot of a direction alternating between
  *     i and opposite(i) from step to step.  Each non-periodic axis gets one
  *     ghost layer beyond its + face in the store (it holds the populations
- *     that face returns).  Not combinable with the learned closure.
+ *     that face returns).
  * AA_SPARSE: the AA pattern over the fluid cells only (sparse indirect
  *     addressing, for domains that solids fill to a large part): fluid cells
  *     are stored compacted in row order, and a table of the q-1 neighbours of

@@ -73,7 +73,7 @@ Launch lattice_launch(const LatticeArgs &a);
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, uint32_t *mask, hipStream_t s);
 hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
-// Esoteric Twist step (lbm_et.hip); no learned closure
+// Esoteric Twist step (lbm_et.hip)
 hipError_t launch_step_et(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
 // sparse addressing (lbm_sparse.hip): neighbour table from the fluid map and
 // the fluid cells' linear indices, and the step; no learned closure

@@ -585,19 +585,53 @@ __device__ inline uint64_t index_t0(const LatticeArgs &a, const SparseArgs &sp, 
     return pidx<Q>(a, i, g.row, g.x);
 }
 
-// Relaxation rates of a cell without the learned closure: the molecular
-// ones, or those of the Smagorinsky relaxation time.
+// Relaxation rates of a cell: the molecular ones, those of the Smagorinsky
+// relaxation time, or those of the learned closure.  The network runs on the
+// matrix cores across the whole wavefront, so with CL_MLP every lane of the
+// wavefront must call this; `active` marks the lanes that hold a fluid cell,
+// and tab is the network's per-lane operand table (in LDS).  A cell whose
+// features leave the trusted range, or whose network output is not finite,
+// falls back to Smagorinsky and is counted in a.fallbacks.
 template <int Q, int CL>
-__device__ inline void relax_rates(const LatticeArgs &a, const float (&d)[Q], float drho, const Macro &M, float &wp,
-                                   float &wm)
+__device__ inline void closure_rates(const LatticeArgs &a, [[maybe_unused]] const uint32_t *tab, const float (&d)[Q],
+                                     float drho, const Macro &M, [[maybe_unused]] bool active, float &wp, float &wm)
 {
     wp = a.omp;
     wm = a.omm;
-    if constexpr (CL == CL_SMAG) {
+    if constexpr (CL == CL_SMAG || CL == CL_MLP) {
         float P[6];
         noneq_flux<Q>(a, d, drho, M, P);
-        trt_rates(a.tau + smag_excess(a.tau, a.cs, flux_norm(P), M.rho), a.magic, wp, wm);
+        const float excess = smag_excess(a.tau, a.cs, flux_norm(P), M.rho);
+        const float tsm = a.tau + excess;
+        float tt = tsm;
+        if constexpr (CL == CL_MLP) {
+            const float ir = rcp(M.rho);
+            float Pn[6], xf[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Pn[k] = P[k] * ir;
+            closure_features(Pn, M.rho, a.tau, excess, xf);
+            const int lane = (threadIdx.y * blockDim.x + threadIdx.x) & 63;
+            const bool inside = features_in_range(a.mlp, xf);
+            float xin[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) xin[k] = inside ? xf[k] : a.mlp[P_MU + k];
+            const float dtau = softplus_fast(mlp_forward_table(tab, xin, lane));
+            const bool use = inside && isfinite(dtau);
+            tt = use ? a.tau + dtau : tsm;
+            const uint64_t fb = __ballot(active && !use);
+            if (lane == 0 && fb) atomicAdd(a.fallbacks, (unsigned long long)__popcll(fb));
+        }
+        trt_rates(tt, a.magic, wp, wm);
     }
+}
+
+// Stage the network's per-lane operand table in LDS (all threads of the
+// workgroup take part; the caller's barrier follows).
+__device__ inline void stage_mlp_table(const LatticeArgs &a, uint32_t *tab_lds)
+{
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int nthr = blockDim.x * blockDim.y;
+    for (int k = tid; k < TAB_WORDS * 64; k += nthr) tab_lds[k] = a.mlp_tab[k];
 }
 
 // Value a cut link returns to its own cell (deviation form).  The face's

@@ -42,12 +42,28 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collid
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
-    if (x >= a.nx || y >= a.ny) return;
-    const Geom g = make_geom(a, x, y, z);
+    // With the learned closure every lane stays to the end (the network runs
+    // across the wavefront); otherwise lanes outside the domain or on solid
+    // cells leave at once.
+    bool active = x < a.nx && y < a.ny;
+    if constexpr (CL != CL_MLP) {
+        if (!active) return;
+    }
+    [[maybe_unused]] const uint32_t *tab = nullptr;
+    if constexpr (CL == CL_MLP) {
+        __shared__ uint32_t tab_lds[TAB_WORDS * 64];
+        stage_mlp_table(a, tab_lds);
+        __syncthreads();
+        tab = tab_lds;
+    }
+    const Geom g = make_geom(a, active ? x : 0, active ? y : 0, z);
     uint32_t m = 0;
     if constexpr (MASK) {
-        m = a.mask[g.c];
-        if (m & SELF_SOLID) return;
+        m = active ? a.mask[g.c] : 0u;
+        if (m & SELF_SOLID) {
+            if constexpr (CL != CL_MLP) return;
+            active = false;
+        }
     }
     typename S::T *A = (typename S::T *)a.pdf;
     float d[Q];
@@ -57,17 +73,20 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collid
         constexpr int i = decltype(I)::value;
         constexpr bool nt = LBM_NT_POLICY == 2 || (LBM_NT_POLICY == 1 && cdir(i, 0) >= 0);
         const uint64_t k = et_index<Q>(a, g, twist(i, odd), cdir(i, 0) < 0, cdir(i, 1) < 0, cdir(i, 2) < 0);
-        d[i] = S::template ld<nt>(A + k);
+        d[i] = (CL != CL_MLP || active) ? S::template ld<nt>(A + k) : 0.f;
     });
 
     float drho;
     const Macro M = moments<Q>(a, d, drho);
     float wp, wm;
-    relax_rates<Q, CL>(a, d, drho, M, wp, wm);
+    closure_rates<Q, CL>(a, tab, d, drho, M, active, wp, wm);
     if constexpr (COLL == COLL_MRT)
         mrt_collide<Q>(a, d, drho, M, wp);
     else
         trt_collide<Q>(a, d, drho, M, wp, wm);
+    if constexpr (CL == CL_MLP) {
+        if (!active) return;
+    }
 
     for_dirs<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -85,6 +104,15 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collid
 template <int Q, int ST, int COLL>
 static void et_coll(const LatticeArgs &a, int cl, bool mk, int odd, const Launch &L, hipStream_t s)
 {
+    if constexpr (COLL == COLL_TRT) {
+        if (cl == CL_MLP) {  // the learned closure runs with the TRT collision
+            if (mk)
+                k_stream_collide_et<Q, ST, CL_MLP, true, COLL><<<L.grid, L.block, 0, s>>>(a, odd);
+            else
+                k_stream_collide_et<Q, ST, CL_MLP, false, COLL><<<L.grid, L.block, 0, s>>>(a, odd);
+            return;
+        }
+    }
     if (cl == CL_NONE) {
         if (mk)
             k_stream_collide_et<Q, ST, CL_NONE, true, COLL><<<L.grid, L.block, 0, s>>>(a, odd);
@@ -100,7 +128,7 @@ static void et_coll(const LatticeArgs &a, int cl, bool mk, int odd, const Launch
 
 hipError_t launch_step_et(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s)
 {
-    if (cl == CL_MLP) return hipErrorInvalidValue;
+    if (cl == CL_MLP && coll == COLL_MRT) return hipErrorInvalidValue;
     const Launch L = lattice_launch(a);
     const bool mk = a.mask != nullptr;
     return dispatch(q, st, [&](auto Qc, auto STc) {

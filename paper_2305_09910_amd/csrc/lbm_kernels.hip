@@ -56,9 +56,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collid
     if constexpr (CL == CL_MLP) {
         // the per-lane operand table of the network, staged once per workgroup
         __shared__ uint32_t tab_lds[TAB_WORDS * 64];
-        const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-        const int nthr = blockDim.x * blockDim.y;
-        for (int k = tid; k < TAB_WORDS * 64; k += nthr) tab_lds[k] = a.mlp_tab[k];
+        stage_mlp_table(a, tab_lds);
         __syncthreads();
         tab = tab_lds;
     }
@@ -103,32 +101,8 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collid
 
     float drho;
     const Macro M = moments<Q>(a, d, drho);
-    float wp = a.omp, wm = a.omm;
-    if constexpr (CL == CL_SMAG || CL == CL_MLP) {
-        float P[6];
-        noneq_flux<Q>(a, d, drho, M, P);
-        const float excess = smag_excess(a.tau, a.cs, flux_norm(P), M.rho);
-        const float tsm = a.tau + excess;
-        float tt = tsm;
-        if constexpr (CL == CL_MLP) {
-            const float ir = rcp(M.rho);
-            float Pn[6], xf[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) Pn[k] = P[k] * ir;
-            closure_features(Pn, M.rho, a.tau, excess, xf);
-            const int lane = (threadIdx.y * blockDim.x + threadIdx.x) & 63;
-            const bool inside = features_in_range(a.mlp, xf);
-            float xin[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) xin[k] = inside ? xf[k] : a.mlp[P_MU + k];
-            const float dtau = softplus_fast(mlp_forward_table(tab, xin, lane));
-            const bool use = inside && isfinite(dtau);
-            tt = use ? a.tau + dtau : tsm;
-            const uint64_t fb = __ballot(active && !use);
-            if (lane == 0 && fb) atomicAdd(a.fallbacks, (unsigned long long)__popcll(fb));
-        }
-        trt_rates(tt, a.magic, wp, wm);
-    }
+    float wp, wm;
+    closure_rates<Q, CL>(a, tab, d, drho, M, active, wp, wm);
     if constexpr (COLL == COLL_MRT)
         mrt_collide<Q>(a, d, drho, M, wp, keep);
     else

@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) k_stream_collide_sparse(LatticeArgs a, Sp
     float drho;
     const Macro M = moments<Q>(a, d, drho);
     float wp, wm;
-    relax_rates<Q, CL>(a, d, drho, M, wp, wm);
+    closure_rates<Q, CL>(a, nullptr, d, drho, M, true, wp, wm);
     if constexpr (COLL == COLL_MRT)
         mrt_collide<Q>(a, d, drho, M, wp);
     else

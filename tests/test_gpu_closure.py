@@ -150,11 +150,11 @@ def test_closure_dataset_matches_oracle():
     assert np.allclose(xg.cpu().numpy(), xo, rtol=1e-5, atol=1e-12)
 
 
-def _mlp_pair(shape, params, norm, steps, q=19, tau=0.51, init="channel"):
+def _mlp_pair(shape, params, norm, steps, q=19, tau=0.51, init="channel", streaming="aa"):
     lbm = _lbm()
     F = (3e-6, 0, 0)
     bc = ("periodic", "periodic", "noslip", "noslip", "periodic", "periodic")
-    g = lbm.Lattice(shape, q=q, tau=tau, force=F, bc=bc, closure="mlp", cs=0.1)
+    g = lbm.Lattice(shape, q=q, tau=tau, force=F, bc=bc, closure="mlp", cs=0.1, streaming=streaming)
     g.set_closure_weights(np.r_[params, norm].astype(np.float32))
     o = oracle.Sim(q, shape, bc=(0, 0, 1, 1, 0, 0), tau=tau, force=F, closure=oracle.CL_MLP, cs=0.1)
     o.set_mlp(params.astype(np.float32), norm.astype(np.float32))
@@ -182,13 +182,14 @@ def _smooth_net(seed=9):
     return p, norm
 
 
+@pytest.mark.parametrize("streaming", ["aa", "et"])
 @pytest.mark.parametrize("q", [19, 27])
-def test_fused_mlp_closure_matches_oracle(q):
+def test_fused_mlp_closure_matches_oracle(q, streaming):
     """60 steps with a smooth network at tau = 0.55 (a 1e-4 shift of the
     network output moves the oracle's populations by ~3e-6 here, so the
     1e-5 bar measures the kernel, not the flow's sensitivity)."""
     p, norm = _smooth_net()
-    g, o = _mlp_pair((32, 16, 8), p, norm, 60, q, tau=0.55)
+    g, o = _mlp_pair((32, 16, 8), p, norm, 60, q, tau=0.55, streaming=streaming)
     a = g.get_pdfs().cpu().numpy()
     b = o.get_pdfs()
     err = float(np.max(np.abs(a - b) / np.abs(b)))
@@ -197,14 +198,15 @@ def test_fused_mlp_closure_matches_oracle(q):
     assert o.fallbacks == 0
 
 
+@pytest.mark.parametrize("streaming", ["aa", "et"])
 @pytest.mark.parametrize("steps", [1, 2])
-def test_fused_mlp_closure_steps_from_nonequilibrium(steps):
+def test_fused_mlp_closure_steps_from_nonequilibrium(steps, streaming):
     """A sharp random network at tau = 0.51 from a non-equilibrium state:
     one even and one odd step, where no error amplification can occur."""
     p, norm = net(9, b3=-6.0)
     norm[:6] = 0.0
     norm[6:12] = [1e-4, 1e-4, 1e-4, 1e-3, 1e-3, 0.5]
-    g, o = _mlp_pair((32, 16, 8), p, norm, steps, 19, tau=0.51, init="noneq")
+    g, o = _mlp_pair((32, 16, 8), p, norm, steps, 19, tau=0.51, init="noneq", streaming=streaming)
     a = g.get_pdfs().cpu().numpy()
     b = o.get_pdfs()
     err = float(np.max(np.abs(a - b) / np.abs(b)))

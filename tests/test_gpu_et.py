@@ -1,7 +1,7 @@
 """Esoteric Twist streaming on the GPU beyond the oracle parity cases of
-test_gpu_parity.py (which run every scheme): the two in-place schemes give
-the same populations, in every storage format, and the learned closure is
-refused with the Esoteric Twist."""
+test_gpu_parity.py (which run every scheme): the Esoteric Twist and the AA
+pattern give the same populations, in every storage format, with every
+closure (the learned one included)."""
 import numpy as np
 import pytest
 
@@ -75,11 +75,41 @@ def lbm_weights(q):
     return oracle.velocity_set(q)[1]
 
 
-def test_et_refuses_the_learned_closure():
+@pytest.mark.parametrize("q", [19, 27])
+def test_et_learned_closure_agrees_with_aa(q):
+    """The learned closure fused into the Esoteric Twist kernel, with solids,
+    velocity / pressure / no-slip faces and a force: the same network on the
+    same values as the AA kernel, so the two differ only by FP32 rounding
+    order (the FP32 bound of test_et_agrees_with_aa), and neither falls back."""
     from paper_2305_09910_amd import lbm
-    with pytest.raises(lbm.LBMError) as exc:
-        lbm.Lattice((16, 8, 8), closure="mlp", streaming="et")
-    assert exc.value.code == lbm.LBM_EINVAL
+    from test_gpu_closure import _smooth_net
+    shape = (40, 18, 12)
+    solid = np.zeros(shape[::-1], np.uint8)
+    solid[3:7, 5:9, 10:15] = 1
+    uw = np.zeros((6, 3))
+    uw[0] = (0.03, 0.002, 0.0)
+    kw = dict(q=q, tau=0.56, force=(1e-5, 0, -2e-6), bc=("velocity", "pressure", "noslip", "noslip", "periodic",
+                                                          "periodic"), u_bc=uw, solid=solid, closure="mlp")
+    print(f"[case] q={q} mlp", flush=True)
+    p, norm = _smooth_net()
+    a = lbm.Lattice(shape, streaming="aa", **kw)
+    e = lbm.Lattice(shape, streaming="et", **kw)
+    rho, u = inputs.uniform_flow(*shape, (0.03, 0.0, 0.0))
+    u += inputs.perturbation(u.shape, 0.005, seed=q)
+    u[:, solid == 1] = 0.0
+    for g in (a, e):
+        g.set_closure_weights(np.r_[p, norm].astype(np.float32))
+        g.init_equilibrium(rho, u)
+    fluid = torch.as_tensor(solid == 0, device=a.device)
+    for n in (1, 40, 41):
+        a.step(n - a.time)
+        e.step(n - e.time)
+        fa, fe = a.get_pdfs(), e.get_pdfs()
+        diff = float((fa - fe)[:, fluid].abs().max())
+        bound = n * 4 * 2.0 ** -24 * float(fa[:, fluid].abs().max())
+        print(f"n={n}: max |f_aa - f_et| = {diff:.3e} (bound {bound:.3e})")
+        assert diff <= bound, (n, diff, bound)
+    assert a.closure_fallbacks() == 0 and e.closure_fallbacks() == 0
 
 
 @pytest.mark.parametrize("q,storage,closure,collision", [

@@ -135,6 +135,7 @@ def _timing_network(seed=9):
     ("channel_256x128x128", "f32", "aa", "mlp"),
     ("channel_512x256x256", "f32", "aa", "mlp"),
     ("channel_256x128x128", "f32", "et", "none"),
+    ("channel_256x128x128", "f32", "et", "mlp"),
     ("channel_512x256x256", "f32", "et", "none"),
     ("channel_512x256x256", "f16", "et", "none"),
     ("obstacles_384_d3q27", "f32", "et", "none"),
