@@ -104,7 +104,7 @@ enum { LBM_COLL_TRT = 0, LBM_COLL_MRT = 1 };
  *     are stored compacted in row order, and a table of the q-1 neighbours of
  *     each fluid cell (4 bytes each) serves the odd steps.  The population
  *     store and the table are sized by the fluid cells (see
- *     lbm_workspace_bytes_flags).  Not combinable with the learned closure.
+ *     lbm_workspace_bytes_flags).
  * All give the same populations up to FP32 rounding order (the same
  * arithmetic runs on the same values). */
 enum { LBM_STREAM_AA = 0, LBM_STREAM_ET = 1, LBM_STREAM_AA_SPARSE = 2 };

@@ -76,7 +76,7 @@ hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int coll, in
 // Esoteric Twist step (lbm_et.hip)
 hipError_t launch_step_et(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
 // sparse addressing (lbm_sparse.hip): neighbour table from the fluid map and
-// the fluid cells' linear indices, and the step; no learned closure
+// the fluid cells' linear indices, and the step
 hipError_t launch_build_sparse_table(const LatticeArgs &a, const SparseArgs &sp, int q, const uint32_t *fcell,
                                      uint32_t *table, hipStream_t s);
 hipError_t launch_step_sparse(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int cl, int coll, int odd,

@@ -208,8 +208,6 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
             return fail(nullptr, LBM_EINVAL, "axis %d: a periodic face needs a periodic opposite face", a);
     if (d->collision != LBM_COLL_TRT && d->collision != LBM_COLL_MRT)
         return fail(nullptr, LBM_EINVAL, "unknown collision %d", d->collision);
-    if (d->streaming == LBM_STREAM_AA_SPARSE && d->closure == LBM_LES_MLP)
-        return fail(nullptr, LBM_EINVAL, "the learned closure runs with dense streaming (AA or Esoteric Twist) only");
     if (d->collision == LBM_COLL_MRT) {
         if (d->closure == LBM_LES_MLP) return fail(nullptr, LBM_EINVAL, "the MLP closure runs with TRT only");
         for (int k = 0; k < 5; ++k)

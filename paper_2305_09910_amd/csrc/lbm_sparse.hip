@@ -54,7 +54,21 @@ __global__ void __launch_bounds__(256) k_stream_collide_sparse(LatticeArgs a, Sp
 {
     using S = Store<ST>;
     const uint32_t k = sparse_block(odd) * 256u + threadIdx.x;
-    if (k >= sp.nf) return;
+    // With the learned closure every lane stays to the end (the network runs
+    // across the wavefront), but lanes past the last fluid cell touch no
+    // memory; otherwise they leave at once.
+    const bool active = k < sp.nf;
+    if constexpr (CL != CL_MLP) {
+        if (!active) return;
+    }
+    [[maybe_unused]] const uint32_t *tab = nullptr;
+    if constexpr (CL == CL_MLP) {
+        __shared__ uint32_t tab_lds[TAB_WORDS * 64];
+        stage_mlp_table(a, tab_lds);
+        __syncthreads();
+        tab = tab_lds;
+    }
+    const bool mem = CL != CL_MLP || active;
     typename S::T *A = (typename S::T *)a.pdf;
     // neighbour table: all q - 1 entries on the odd step (each serves one
     // read and one write), only with velocity/pressure faces on the even one
@@ -64,12 +78,14 @@ __global__ void __launch_bounds__(256) k_stream_collide_sparse(LatticeArgs a, Sp
     const bool need = odd || a.any_vp;
     for_dirs<1, Q>([&](auto J) {
         constexpr int j = decltype(J)::value;
-        t[j] = need ? __builtin_nontemporal_load(sp.nbt + sp_table<Q>(k, j)) : NB_SOLID;
+        t[j] = need && mem ? __builtin_nontemporal_load(sp.nbt + sp_table<Q>(k, j)) : NB_SOLID;
     });
     float d[Q];
     for_dirs<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        if (i == 0 || !odd) {
+        if (!mem) {
+            d[i] = 0.f;
+        } else if (i == 0 || !odd) {
             d[i] = S::template ld<true>(A + sp_index<Q>(k, i));
         } else {
             const uint32_t s = t[opp(i)];  // neighbour x - c_i
@@ -80,11 +96,14 @@ __global__ void __launch_bounds__(256) k_stream_collide_sparse(LatticeArgs a, Sp
     float drho;
     const Macro M = moments<Q>(a, d, drho);
     float wp, wm;
-    closure_rates<Q, CL>(a, nullptr, d, drho, M, true, wp, wm);
+    closure_rates<Q, CL>(a, tab, d, drho, M, active, wp, wm);
     if constexpr (COLL == COLL_MRT)
         mrt_collide<Q>(a, d, drho, M, wp);
     else
         trt_collide<Q>(a, d, drho, M, wp, wm);
+    if constexpr (CL == CL_MLP) {
+        if (!active) return;
+    }
 
     for_dirs<0, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -143,6 +162,12 @@ hipError_t launch_build_sparse_table(const LatticeArgs &a, const SparseArgs &sp,
 template <int Q, int ST, int COLL>
 static void sparse_coll(const LatticeArgs &a, const SparseArgs &sp, int cl, int odd, dim3 grid, hipStream_t s)
 {
+    if constexpr (COLL == COLL_TRT) {
+        if (cl == CL_MLP) {  // the learned closure runs with the TRT collision
+            k_stream_collide_sparse<Q, ST, CL_MLP, COLL><<<grid, 256, 0, s>>>(a, sp, odd);
+            return;
+        }
+    }
     if (cl == CL_NONE)
         k_stream_collide_sparse<Q, ST, CL_NONE, COLL><<<grid, 256, 0, s>>>(a, sp, odd);
     else
@@ -152,7 +177,7 @@ static void sparse_coll(const LatticeArgs &a, const SparseArgs &sp, int cl, int 
 hipError_t launch_step_sparse(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int cl, int coll, int odd,
                               hipStream_t s)
 {
-    if (cl == CL_MLP) return hipErrorInvalidValue;
+    if (cl == CL_MLP && coll == COLL_MRT) return hipErrorInvalidValue;
     if (sp.nf == 0) return hipSuccess;
     const dim3 grid((sp.nf + 255) / 256);
     return dispatch(q, st, [&](auto Qc, auto STc) {

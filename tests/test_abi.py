@@ -125,8 +125,8 @@ def _create(L, d, q=19, tau=0.6, flags=None):
     return rc, h
 
 
-@pytest.mark.parametrize("case", ["tau", "pairing", "bcenum", "null_ws", "small_ws", "align", "flags", "sparse_mlp",
-                                  "mrt_mlp", "sparse_small_ws"])
+@pytest.mark.parametrize("case", ["tau", "pairing", "bcenum", "null_ws", "small_ws", "align", "flags", "mrt_mlp",
+                                  "sparse_small_ws"])
 def test_create_rejects_before_device(L, case):
     d = lbm.make_domain((8, 8, 8))
     need = lbm.workspace_bytes(d, 19)
@@ -151,10 +151,6 @@ def test_create_rejects_before_device(L, case):
         flags = ctypes.cast(buf, ctypes.c_void_p)
     elif case == "mrt_mlp":
         d.collision = lbm.COLLISION["mrt"]
-        d.closure = lbm.CLOSURE["mlp"]
-        d.workspace_bytes = lbm.workspace_bytes(d, 19)
-    elif case == "sparse_mlp":
-        d.streaming = lbm.STREAMING["sparse"]
         d.closure = lbm.CLOSURE["mlp"]
         d.workspace_bytes = lbm.workspace_bytes(d, 19)
     elif case == "sparse_small_ws":

@@ -182,7 +182,7 @@ def _smooth_net(seed=9):
     return p, norm
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", ["aa", "et", "sparse"])
 @pytest.mark.parametrize("q", [19, 27])
 def test_fused_mlp_closure_matches_oracle(q, streaming):
     """60 steps with a smooth network at tau = 0.55 (a 1e-4 shift of the
@@ -198,7 +198,7 @@ def test_fused_mlp_closure_matches_oracle(q, streaming):
     assert o.fallbacks == 0
 
 
-@pytest.mark.parametrize("streaming", ["aa", "et"])
+@pytest.mark.parametrize("streaming", ["aa", "et", "sparse"])
 @pytest.mark.parametrize("steps", [1, 2])
 def test_fused_mlp_closure_steps_from_nonequilibrium(steps, streaming):
     """A sharp random network at tau = 0.51 from a non-equilibrium state:

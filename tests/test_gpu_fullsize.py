@@ -142,6 +142,7 @@ def _timing_network(seed=9):
     ("porous_256", "f32", "aa", "none"),
     ("porous_256", "f32", "sparse", "none"),
     ("porous_256", "f16", "sparse", "none"),
+    ("porous_256", "f32", "sparse", "mlp"),
     ("obstacles_384_d3q27", "f32", "sparse", "none"),
 ])
 def test_closure_et_and_sparse_forms_sampled_against_probe(name, storage, streaming, closure):

@@ -1,8 +1,8 @@
 """Sparse addressing (the AA pattern over the fluid cells only) on the GPU,
 beyond the oracle parity cases of test_gpu_parity.py (which run every
 scheme): porous media against the oracle, agreement with the dense AA
-kernel in every storage format and with every boundary kind, state
-functions, and the refusal of the learned closure."""
+kernel in every storage format, with every boundary kind and with the
+learned closure, and the state functions."""
 import numpy as np
 import pytest
 
@@ -154,8 +154,41 @@ def test_state_functions_and_checkpoint():
     assert torch.equal(t.get_pdfs(), s.get_pdfs())
 
 
-def test_sparse_refuses_the_learned_closure():
+@pytest.mark.parametrize("q", [19, 27])
+def test_learned_closure_in_porous_medium(q):
+    """The learned closure fused into the sparse kernel on a 50%-solid porous
+    medium with inlet/outlet faces: against the dense AA kernel (the same
+    network on the same values; FP32 rounding order only) and against the
+    oracle (1e-5), with no fallbacks.  The fluid count is not a multiple of
+    64, so the last wavefront carries idle lanes through the network."""
     from paper_2305_09910_amd import lbm
-    with pytest.raises(lbm.LBMError) as exc:
-        lbm.Lattice((16, 8, 8), closure="mlp", streaming="sparse")
-    assert exc.value.code == lbm.LBM_EINVAL
+    from test_gpu_closure import _smooth_net
+    shape = (44, 20, 14)
+    solid, rho, u = _medium(shape, 0.5, seed=7 * q)
+    assert int((solid == 0).sum()) % 64 != 0
+    uw = np.zeros((6, 3))
+    uw[0] = (0.01, 0.001, 0.0)
+    kw = dict(q=q, tau=0.56, force=(1e-5, 0, -2e-6), bc=INOUT, u_bc=uw, solid=solid, closure="mlp", cs=0.1)
+    print(f"[case] q={q} mlp", flush=True)
+    p, norm = _smooth_net()
+    a = lbm.Lattice(shape, streaming="aa", **kw)
+    s = lbm.Lattice(shape, streaming="sparse", **kw)
+    for g in (a, s):
+        g.set_closure_weights(np.r_[p, norm].astype(np.float32))
+        g.init_equilibrium(rho, u)
+    o = oracle.Sim(q, shape, bc=tuple(BCS[b] for b in INOUT), tau=0.56, force=(1e-5, 0, -2e-6), u_bc=uw, solid=solid,
+                   closure=oracle.CL_MLP, cs=0.1)
+    o.set_mlp(p.astype(np.float32), norm.astype(np.float32))
+    o.init_equilibrium(rho, u)
+    fluid = torch.as_tensor(solid == 0, device=a.device)
+    for n in (1, 40, 41):
+        a.step(n - a.time)
+        s.step(n - s.time)
+        o.step(n - (0 if n == 1 else (1 if n == 40 else 40)))
+        fa, fs = a.get_pdfs(), s.get_pdfs()
+        diff = float((fa - fs)[:, fluid].abs().max())
+        bound = n * 4 * 2.0 ** -24 * float(fa[:, fluid].abs().max())
+        err = _max_rel(s, o, solid)
+        print(f"n={n}: max |f_dense - f_sparse| = {diff:.3e} (bound {bound:.3e}), vs oracle {err:.3e}")
+        assert diff <= bound and err <= 1e-5
+    assert a.closure_fallbacks() == 0 and s.closure_fallbacks() == 0
