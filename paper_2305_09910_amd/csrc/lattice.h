@@ -112,6 +112,9 @@ struct Store<ST_F16> {
     template <bool NT = false>
     __device__ static void st(T *p, float v) { st_pop<NT>(p, (_Float16)v); }
     __device__ static T cvt(float v) { return (_Float16)v; }
+    // raw 16-bit patterns (two cells packed in one 32-bit access)
+    __device__ static float from_bits(uint32_t b) { return (float)__builtin_bit_cast(_Float16, (uint16_t)b); }
+    __device__ static uint32_t to_bits(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
 };
 
 // bfloat16 as raw bits: widen by a shift, narrow with the hardware
@@ -126,6 +129,8 @@ struct Store<ST_BF16> {
     template <bool NT = false>
     __device__ static void st(T *p, float v) { st_pop<NT>(p, f32_to_bf16_rne(v)); }
     __device__ static T cvt(float v) { return f32_to_bf16_rne(v); }
+    __device__ static float from_bits(uint32_t b) { return __uint_as_float((b & 0xffffu) << 16); }
+    __device__ static uint32_t to_bits(float v) { return f32_to_bf16_rne(v); }
 };
 
 // ---------------------------------------------------------------------------

@@ -70,6 +70,40 @@ def test_et_agrees_with_aa(q, storage):
     assert abs(ma - me) <= 1e-6 * ma and np.abs(pa - pe).max() <= 1e-6 * ma
 
 
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_paired_16bit_even_step(q, storage):
+    """16-bit storage without a mask on rows of a multiple of 128 cells: the
+    AA even step runs two cells per thread (one 32-bit access per direction),
+    with velocity / pressure / no-slip faces on both ends of the pairs' rows
+    and a force.  The Esoteric Twist runs one cell per thread; the two differ
+    only by FP32 rounding order (the bound of test_et_agrees_with_aa)."""
+    from paper_2305_09910_amd import lbm
+    shape = (128, 12, 6)
+    uw = np.zeros((6, 3))
+    uw[0] = (0.03, 0.002, 0.0)
+    kw = dict(q=q, tau=0.58, force=(1e-5, 0, -2e-6), bc=("velocity", "pressure", "noslip", "noslip", "periodic",
+                                                          "periodic"), u_bc=uw, storage=storage)
+    print(f"[case] q={q} storage={storage} paired even step", flush=True)
+    a = lbm.Lattice(shape, streaming="aa", **kw)
+    e = lbm.Lattice(shape, streaming="et", **kw)
+    rho, u = inputs.uniform_flow(*shape, (0.03, 0.0, 0.0))
+    u += inputs.perturbation(u.shape, 0.005, seed=3 * q)
+    for g in (a, e):
+        g.init_equilibrium(rho, u)
+    w = torch.as_tensor(lbm_weights(q), device=a.device, dtype=torch.float64)[:, None, None, None]
+    for n in (1, 50, 51):
+        a.step(n - a.time)
+        e.step(n - e.time)
+        fa, fe = a.get_pdfs(), e.get_pdfs()
+        dmax = float((fa - w).abs().max())
+        rel = 2.0 ** -10 if storage == "f16" else 2.0 ** -7
+        bound = n * 2 * rel * 2.0 ** np.floor(np.log2(dmax))
+        diff = float((fa - fe).abs().max())
+        print(f"n={n}: max |f_aa - f_et| = {diff:.3e} (bound {bound:.3e})")
+        assert diff <= bound, (n, diff, bound)
+
+
 def lbm_weights(q):
     import oracle
     return oracle.velocity_set(q)[1]
