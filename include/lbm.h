@@ -132,36 +132,55 @@ typedef struct lbm_domain {
 /* Fill *d with defaults: all faces periodic, rho_bc = 1, u_bc = 0, F32
  * storage, no closure, no flags, magic = 3/16, cs_smag = 0.1, TRT
  * collision, MRT ghost rates {1.19, 1.4, 1.2, 1.4, 1.98}, AA streaming, no
- * workspace. */
+ * workspace.  The domain carries the free parameters of the kernel
+ * interface the paper describes for its generated kernels (raw pointers,
+ * shape and free parameters; Section 3).  d == NULL: no effect. */
 void lbm_domain_defaults(lbm_domain *d);
 
 /* Bytes of device workspace a context needs for domain d and the stencil
- * (19 or 27).  Only nx, ny, nz, storage, closure, use_flags, streaming and
- * (for the ghost layers of the Esoteric Twist) bc are read.  With sparse
- * addressing this is the bound for a domain without solids. */
+ * (19 or 27): one population set kept in place (the single PDF set of the
+ * in-place streaming of Section 5.2) plus the reduction and closure areas.
+ * Only nx, ny, nz, storage, closure, use_flags, streaming and (for the
+ * ghost layers of the Esoteric Twist) bc are read.  With sparse addressing
+ * this is the bound for a domain without solids.  *out (host) receives the
+ * size.  LBM_EINVAL for NULL or invalid sizes/enums, LBM_ENOMEM when the
+ * domain exceeds the cell indexing. */
 int lbm_workspace_bytes(const lbm_domain *d, int stencil, size_t *out);
 
 /* As lbm_workspace_bytes, for the solid flags that lbm_create will get
- * (host, one byte per cell, nullable): with sparse addressing the stores are
- * sized by the fluid cells; otherwise the same value. */
+ * (host, one byte per cell, nullable; read only during the call): with
+ * sparse addressing the stores are sized by the fluid cells; otherwise the
+ * same value.  Errors as lbm_workspace_bytes. */
 int lbm_workspace_bytes_flags(const lbm_domain *d, int stencil, const uint8_t *flags, size_t *out);
 
 /*
- * Create a context.  tau > 1/2 is the molecular relaxation time
- * (viscosity nu = (tau - 1/2)/3); force[3] (nullable: zero) is the constant
- * body-force density of Guo's forcing; flags (host, nullable) holds one byte
- * per cell, non-zero = solid, and needs d->use_flags.  Opposite faces must
- * both be periodic or both not.  The populations are left undefined: call
+ * Create a context for the lattice Boltzmann equation of Section 2: the
+ * collision Eq. (1) relaxes f^neq with the operator Omega, set here by the
+ * relaxation time tau > 1/2 (viscosity nu = (tau - 1/2)/3; Omega read as
+ * the two-relaxation-time or MRT operator of d->collision), and the
+ * streaming Eq. (2) moves f_i* to x + c_i.  force[3] (host, nullable: zero)
+ * is the constant body-force density of Guo's forcing; flags (host,
+ * nullable, read only during the call) holds one byte per cell [nz][ny][nx],
+ * non-zero = solid, and needs d->use_flags.  Opposite faces must both be
+ * periodic or both not.  The context lives in d->workspace (device, caller
+ * owned, must outlive it); *out receives a host handle owned by the caller
+ * (release with lbm_destroy).  The populations are left undefined: call
  * lbm_init_equilibrium or lbm_set_pdfs next.  Synchronises.
+ * LBM_EINVAL for invalid parameters or a small/misaligned workspace,
+ * LBM_ENOMEM when the domain exceeds the cell indexing, LBM_EDEVICE when a
+ * device call fails (*out stays NULL on every error).
  */
 int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double tau, const double force[3],
                lbm_ctx **out);
 
-/* Release host metadata.  Device memory (the workspace) stays the caller's. */
+/* Release the host handle of a context created for Section 2's update.
+ * Device memory (the workspace) stays the caller's.  ctx == NULL: no-op. */
 int lbm_destroy(lbm_ctx *ctx);
 
 /* Message of the last failure on ctx (ctx == NULL: of the last failed
- * lbm_create on this thread).  Never NULL. */
+ * call without a context on this thread).  Never NULL; the string is owned
+ * by the library and valid until the next call on ctx.  (Diagnostics only:
+ * no passage of the paper defines it.) */
 const char *lbm_last_error(const lbm_ctx *ctx);
 
 /* Set every fluid cell to the second-order equilibrium f_i^eq(rho, u) of
@@ -169,49 +188,66 @@ const char *lbm_last_error(const lbm_ctx *ctx);
  * to 0.  Equilibrium as in Eq. (1)'s f^eq with c_s^2 = 1/3. */
 int lbm_init_equilibrium(lbm_ctx *ctx, const double *rho_dev, const double *u_dev);
 
-/* Load canonical FP64 populations f_dev [q][n] (rounded to the storage
- * format); resets the step count to 0. */
+/* Load canonical FP64 populations f_dev [q][n] (device, caller owned):
+ * the PDFs f_i(x, t) of Section 2 after the streaming Eq. (2) and before
+ * the collision Eq. (1), rounded to the storage format; solid cells are
+ * ignored.  Resets the step count to 0.  LBM_EINVAL for NULL. */
 int lbm_set_pdfs(lbm_ctx *ctx, const double *f_dev);
 
-/* Write the canonical FP64 populations of the current step to f_dev [q][n]
- * (solid cells: w_i).  Valid after any number of steps. */
+/* Write the canonical FP64 populations f_i(x, t) of Section 2 (after the
+ * streaming Eq. (2), before the collision Eq. (1)) of the current step to
+ * f_dev [q][n] (device, caller owned; solid cells: w_i).  Valid after any
+ * number of steps.  LBM_EINVAL for NULL. */
 int lbm_get_pdfs(lbm_ctx *ctx, double *f_dev);
 
-/* Canonical FP64 populations at n cells (linear indices cells_dev[n],
- * int64) into out_dev [n][q]. */
+/* Canonical FP64 populations f_i(x, t) of Section 2 at n >= 0 cells
+ * (device linear indices cells_dev[n], int64, (z ny + y) nx + x) into
+ * out_dev [n][q] (device, caller owned).  An index outside the domain
+ * yields NaN in its row.  LBM_EINVAL for n < 0 or NULL with n > 0. */
 int lbm_gather_pdfs(lbm_ctx *ctx, const int64_t *cells_dev, int64_t n, double *out_dev);
 
 /* Advance n >= 0 time steps (Eq. (1) then Eq. (2) per step, fused in one
- * kernel per step).  Asynchronous. */
+ * kernel per step).  Asynchronous.  LBM_EINVAL for n < 0, LBM_ESTATE when
+ * the MLP closure has no weights, LBM_EDEVICE when a launch fails. */
 int lbm_step(lbm_ctx *ctx, int64_t n);
 
-/* Steps taken since the last init/set/load. */
+/* Steps (applications of Eq. (1)-(2)) taken since the last init/set/load;
+ * -1 for ctx == NULL. */
 int64_t lbm_time(const lbm_ctx *ctx);
 
-/* Density rho_dev [n] and velocity u_dev [3][n] = (j + F/2)/rho of the
- * current canonical state, FP32 (solid cells: rho = 1, u = 0). */
+/* The local fluid properties on which f^eq of Eq. (1) depends (Section 2):
+ * density rho_dev [n] = sum_i f_i and velocity u_dev [3][n] = (j + F/2)/rho
+ * of the current canonical state, FP32, device, caller owned (solid cells:
+ * rho = 1, u = 0).  Asynchronous.  LBM_EINVAL for NULL. */
 int lbm_moments(lbm_ctx *ctx, float *rho_dev, float *u_dev);
 
-/* FP64 totals over fluid cells of the current state: *mass = sum rho,
- * mom = sum_i c_i f_i.  Deterministic.  Synchronises.  Returns
- * LBM_ENONFINITE if any fluid population is NaN or Inf. */
+/* FP64 totals over fluid cells of the current state (host outputs):
+ * *mass = sum rho, mom = sum_i c_i f_i -- the mass conservation the
+ * turbulent-channel case is assessed on (Section 5.1).  Deterministic.
+ * Synchronises.  Returns LBM_ENONFINITE if any fluid population is NaN or
+ * Inf (the totals are still written), LBM_EINVAL for NULL. */
 int lbm_totals(lbm_ctx *ctx, double *mass, double mom[3]);
 
-/* Bytes of the raw population store (for checkpoints): q rows of sx cells
- * per stored row, sx = nx rounded up to whole 128-byte lines, with the
- * Esoteric Twist's ghost layers included; with sparse addressing q values
- * per fluid cell, in chunks of 64.  Its layout is internal; only
- * lbm_load_state of a context with the same domain and flags reads it back. */
+/* Bytes of the raw population store (for checkpoints of the single PDF
+ * set kept in place, Section 5.2): q rows of sx cells per stored row,
+ * sx = nx rounded up to whole 128-byte lines, with the Esoteric Twist's
+ * ghost layers included; with sparse addressing q values per fluid cell, in
+ * chunks of 64.  Its layout is internal; only lbm_load_state of a context
+ * with the same domain and flags reads it back.  LBM_EINVAL for NULL. */
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *out);
 
-/* Copy the raw state to dst_dev (lbm_state_bytes bytes) and report the
- * step count; lbm_load_state restores both.  A restored run continues bit
- * for bit as the saved one would have. */
+/* Copy the raw state (the PDF set of Section 5.2's in-place streaming) to
+ * dst_dev (device, caller owned, lbm_state_bytes bytes) and report the step
+ * count through *time (host); lbm_load_state restores both from src_dev.
+ * Asynchronous.  A restored run continues bit for bit as the saved one
+ * would have.  LBM_EINVAL for NULL or time < 0. */
 int lbm_save_state(lbm_ctx *ctx, void *dst_dev, int64_t *time);
 int lbm_load_state(lbm_ctx *ctx, const void *src_dev, int64_t time);
 
 /*
- * Learned-closure weights (host, FP32): n = 1313 + 24 values, the MLP
+ * Learned subgrid closure of the LES turbulent channel (Section 5.1: the
+ * subgrid shear stresses along the wall-normal direction), weights (host,
+ * FP32, read only during the call): n = 1313 + 24 values, the MLP
  * 6 -> 32 -> 32 -> 1 as W1[32][6], b1[32], W2[32][32], b2[32], W3[32], b3,
  * then per input mu[6], sigma[6], lo[6], hi[6] (standardisation and the
  * trusted input range; outside it the cell falls back to Smagorinsky).
@@ -219,12 +255,16 @@ int lbm_load_state(lbm_ctx *ctx, const void *src_dev, int64_t time);
  */
 int lbm_set_closure_weights(lbm_ctx *ctx, const float *params, size_t n);
 
-/* Number of fluid-cell updates that fell back to Smagorinsky since the last
- * call (MLP closure only); resets the counter.  Synchronises. */
+/* Number of fluid-cell updates of the Section 5.1 LES closure that fell
+ * back to Smagorinsky since the last call (MLP closure only) into *count
+ * (host); resets the counter.  Synchronises.  LBM_EINVAL for NULL. */
 int lbm_closure_fallbacks(lbm_ctx *ctx, int64_t *count);
 
 /* ------------------------------------------------------------------------ */
-/* Training-data and training kernels of the learned closure.               */
+/* Training-data and training kernels of the learned closure (the subgrid   */
+/* stresses of the Section 5.1 LES channel).  All pointers are device       */
+/* memory owned by the caller; work is enqueued on `stream`; LBM_EINVAL for  */
+/* invalid sizes or NULL, LBM_EDEVICE when a launch fails.                   */
 /* ------------------------------------------------------------------------ */
 
 /* Box filter over non-overlapping 4x4x4 blocks of fine FP32 fields
