@@ -743,3 +743,215 @@ def test_mrt_taylor_green_decay():
     a1 = amp()
     nu_eff = -math.log(a1 / a0) / 900 / (2 * k * k)
     assert abs(nu_eff / nu - 1) < 0.01
+
+
+# --------------------------------------------------------------------------
+# the closure flux, the Guo source and boundary precedence
+# --------------------------------------------------------------------------
+def _full_tensor(P6):
+    return np.array([[P6[0], P6[3], P6[4]], [P6[3], P6[1], P6[5]], [P6[4], P6[5], P6[2]]])
+
+
+@pytest.mark.parametrize("q", QS)
+@pytest.mark.parametrize("tau", [0.6, 1.0])
+def test_closure_flux_vanishes_in_uniform_acceleration(q, tau):
+    """A fully periodic box of uniform velocity accelerated by a constant force
+    has no velocity gradients, so it carries no viscous stress: the closure
+    flux P_c = sum c c (f - f_eq) + (uF + Fu)/2 must settle at zero (with Guo
+    forcing the non-equilibrium second moment settles at -(uF + Fu)/2).  A
+    dropped correction leaves |P_c| = |uF + Fu|/2, a flipped sign twice that;
+    the collision's own flux (seen through the Smagorinsky relaxation time)
+    must vanish too."""
+    shape = (4, 4, 4)
+    F = np.array([2e-5, 0.0, 1e-5])
+    u0 = np.array([0.05, 0.0, -0.03])
+    sim = oracle.Sim(q, shape, tau=tau, force=F, closure=oracle.CL_SMAG, cs=0.1)
+    u = np.broadcast_to(u0[:, None, None, None], (3, 4, 4, 4)).copy()
+    sim.init_equilibrium(np.ones((4, 4, 4)), u)
+    sim.step(50)
+    fs = sim.get_pdfs()
+    f = fs[:, 1, 2, 3]
+    assert np.abs(fs - f[:, None, None, None]).max() < 1e-15  # the state stays uniform
+    c, _, _ = oracle.velocity_set(q)
+    rho = f.sum()
+    u = (c.T @ f + F / 2) / rho
+    assert abs(u[0] - (u0[0] + 50.5 * F[0])) < 1e-12  # j grows by F per step; u = (j + F/2)/rho
+    scale = np.linalg.norm(0.5 * (np.outer(u, F) + np.outer(F, u)))
+    P = _full_tensor(oracle.noneq_flux(q, f, F))
+    assert np.linalg.norm(P) <= 1e-8 * scale
+    _, tt = oracle.collide(q, f, tau, MAGIC, F=F, closure=oracle.CL_SMAG, cs=0.1)
+    dropped = oracle.smagorinsky_tau(tau, 0.1, scale, rho) - tau  # excess if the flux were |uF + Fu|/2
+    assert tt - tau <= 1e-6 * dropped + 1e-15
+
+
+@pytest.mark.parametrize("q", QS)
+def test_guo_source_moments(q):
+    """With both TRT rates equal to one (tau = 1, Lambda = 1/4: BGK at rate 1)
+    the collision returns f_eq(rho, u) + S/2, which exposes the Guo source S.
+    Its moments are fixed: sum S = 0, sum c S = F, sum c c S = uF + Fu."""
+    c, w, _ = oracle.velocity_set(q)
+    rng = np.random.default_rng(31)
+    for _ in range(5):
+        f = _random_cell(q, rng)
+        F = rng.uniform(-1e-3, 1e-3, 3)
+        rho = f.sum()
+        u = (c.T @ f + F / 2) / rho
+        fs, _ = oracle.collide(q, f, 1.0, 0.25, F=F)
+        S = 2 * (fs - oracle.equilibrium(q, rho, u))
+        # S comes out of f* - f_eq (both ~w_i), so it carries ~1e-16 absolute
+        # roundoff; a dropped or sign-flipped term moves a moment by ~|u||F|
+        scale = np.abs(F).max()
+        assert abs(S.sum()) < 1e-11 * scale
+        assert np.abs(c.T @ S - F).max() < 1e-11 * scale
+        M2 = np.einsum("i,ia,ib->ab", S, c, c)
+        assert np.abs(M2 - (np.outer(u, F) + np.outer(F, u))).max() < 1e-11 * scale
+
+
+@pytest.mark.parametrize("q", QS)
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.5])
+def test_shear_flux_of_steady_poiseuille(q, tau):
+    """In the steady force-driven Poiseuille flow the shear component of the
+    closure flux is the Chapman-Enskog stress of the pre-collision state,
+    P_xy = -(tau/3) rho du/dy, with du/dy of the exact parabola (the forcing
+    correction has no xy part here).  Holds to roundoff at every row,
+    including the wall rows; a (tau - 1/2) in place of tau misses by 17-83%."""
+    ny, F = 16, 1e-5
+    nu = (tau - 0.5) / 3
+    y = np.arange(ny)
+    exact = F / (2 * nu) * (y + 0.5) * (ny - 0.5 - y)
+    sim = oracle.Sim(q, (1, ny, 1), bc=(0, 0, BC_NOSLIP, BC_NOSLIP, 0, 0), tau=tau, magic=MAGIC, force=(F, 0, 0))
+    u = np.zeros((3, 1, ny, 1))
+    u[0] = exact[None, :, None]
+    sim.init_equilibrium(np.ones((1, ny, 1)), u)
+    sim.step(int(6 * ny * ny / nu))
+    f = sim.get_pdfs()[:, 0, :, 0]
+    rho, _ = sim.moments()
+    dudy = F / (2 * nu) * (ny - 1 - 2 * y)
+    expect = -(tau / 3) * rho[0, :, 0] * dudy
+    pxy = np.array([oracle.noneq_flux(q, f[:, k], (F, 0, 0))[3] for k in range(ny)])
+    assert np.abs(pxy - expect).max() < 1e-10 * np.abs(expect).max()
+    others = np.array([oracle.noneq_flux(q, f[:, k], (F, 0, 0))[[4, 5]] for k in range(ny)])
+    assert np.abs(others).max() < 1e-12 * np.abs(expect).max()
+
+
+@pytest.mark.parametrize("vals,sensitive", [
+    # h1 near zero: the roundings of w1 and z survive the rounding of h1
+    ((0.7, -0.2985, -1.3, 0.0013, 2.9, -0.4), ("w1", "z", "w2", "w3", "h2")),
+    # h2 near zero: the roundings of h1, w2, w3 and h2 show in the output
+    ((0.7, 0.1, -1.3, 0.47, 2.9, -0.4), ("h1", "w2", "w3", "h2")),
+])
+def test_mlp_single_path_closed_form_bf16(vals, sensitive):
+    """The bfloat16 forward (every matrix operand rounded to bfloat16, sums and
+    activations in FP64): one non-zero path through the network gives
+    softplus(b(w3) b(tanh(b(w2) b(tanh(b(w1) b(z) + b1)) + b2)) + b3), b()
+    the round-to-nearest-even bfloat16 of torch.  Each case is chosen so that
+    leaving out any of the listed roundings moves the output by > 1e-6 (a
+    later rounding would otherwise mask an earlier one)."""
+    torch = pytest.importorskip("torch")
+
+    def b(v):
+        return float(torch.tensor([v], dtype=torch.float64).float().bfloat16().double()[0])
+
+    p = np.zeros(1313)
+    mu, sigma = 0.05, 0.7
+    norm = np.r_[np.full(6, mu), np.full(6, sigma), -np.ones(6) * 1e9, np.ones(6) * 1e9]
+    w1, b1, w2, b2, w3, b3 = vals
+    p[0 * 6 + 2] = w1  # W1[0][2]
+    p[192 + 0] = b1
+    p[224 + 5 * 32 + 0] = w2  # W2[5][0]
+    p[1248 + 5] = b2
+    p[1280 + 5] = w3
+    p[1312] = b3
+    x = np.full((1, 6), mu)
+    x[0, 2] = 0.35
+    z = (0.35 - mu) / sigma
+
+    def closed_form(skip=None):
+        r = lambda name, v: v if name == skip else b(v)  # noqa: E731
+        h1 = math.tanh(r("w1", w1) * r("z", z) + b1)
+        h2 = math.tanh(r("w2", w2) * r("h1", h1) + b2)
+        return math.log1p(math.exp(r("w3", w3) * r("h2", h2) + b3))
+
+    got = oracle.mlp_forward(p, norm, x, bf16=True)[0]
+    assert abs(got - closed_form()) < 1e-15
+    for name in sensitive:
+        assert abs(closed_form(name) - got) > 1e-6, name
+
+
+def test_closure_dataset_features_pure_shear():
+    """The dataset's six features are those of the flux the coarse lattice would
+    carry, P = -(2/3)(tau + dtau*) S: for a pure shear S_xy with tau_sgs_xy =
+    -2c S_xy that is tr P = 0, |dev P| = sqrt(2) |P_xy|, det dev P = 0,
+    rho - 1 = 0, the Smagorinsky excess of Q = sqrt(2) |P_xy| (root of the
+    Hou quadratic) and tau."""
+    cz, cy, cx = 2, 6, 4
+    z, y, x = np.meshgrid(np.arange(cz), np.arange(cy), np.arange(cx), indexing="ij")
+    g, cc, tau, cs = 2e-3, 0.01, 0.55, 0.1
+    filt = np.zeros((10, cz, cy, cx))
+    filt[0] = 1.0
+    filt[1] = g * (y - 2.5)
+    filt[4 + 3] = filt[1] * filt[2] - 2 * cc * 0.5 * g
+    x6, t = oracle.closure_dataset(filt, periodic=(1, 1, 1), tau=tau, cs=cs)
+    inner = (y.reshape(-1) > 0) & (y.reshape(-1) < cy - 1)
+    pxy = -(2 / 3) * (tau + 3 * cc) * 0.5 * g
+    Q = math.sqrt(2) * abs(pxy)
+    for r in np.nonzero(inner)[0]:
+        f6 = x6[r]
+        assert abs(f6[0]) < 1e-18 and abs(f6[2]) < 1e-12 and f6[3] == 0.0 and f6[5] == tau
+        assert abs(f6[1] - Q) < 1e-15
+        tt = tau + f6[4]
+        assert abs(tt * tt - tau * tt - 4.5 * math.sqrt(2) * cs * cs * Q) < 1e-16
+
+
+def _corner_case(bc, u_bc, q=19, shape=(3, 3, 2), seed=41):
+    """One step of an oracle lattice from seeded non-equilibrium populations;
+    returns the new state and the pre-step state."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    f0 = np.stack([_random_cell(q, rng) for _ in range(nx * ny * nz)], axis=1).reshape(q, nz, ny, nx)
+    sim = oracle.Sim(q, shape, bc=bc, tau=0.7, u_bc=u_bc, force=(1e-4, -2e-5, 0))
+    sim.set_pdfs(f0)
+    sim.step(1)
+    return sim.get_pdfs(), f0
+
+
+@pytest.mark.parametrize("q", QS)
+def test_corner_link_precedence(q):
+    """A link that leaves through two non-periodic faces takes the rule of the
+    first of no-slip, velocity, pressure (the lowest face index among equals).
+    Checked against domains where the same link crosses only the deciding
+    face: the collision is local, so the returning population must agree bit
+    for bit."""
+    c, _, opp = oracle.velocity_set(q)
+    uw = np.zeros((6, 3))
+    uw[0] = (0.04, 0.01, 0)
+    uw[2] = (-0.02, 0, 0.03)
+    V, P, N, X = BC_VELOCITY, BC_PRESSURE, BC_NOSLIP, BC_PERIODIC
+
+    def slot(f, i, x, y):  # the slot opposite(i) of cell (x, y, 0) after the step
+        return f[opp[i], 0, y, x]
+
+    def dir_of(v):
+        return int(np.nonzero((c == np.array(v)).all(axis=1))[0][0])
+
+    # no-slip (-y) against velocity (-x): corner (0, 0), link (-1, -1, 0)
+    a, _ = _corner_case((V, P, N, N, X, X), uw, q)
+    b, _ = _corner_case((X, X, N, N, X, X), uw, q)
+    i = dir_of((-1, -1, 0))
+    assert slot(a, i, 0, 0) == slot(b, i, 0, 0)
+    # and the velocity face alone moves the value (the rules do differ)
+    d, _ = _corner_case((V, P, X, X, X, X), uw, q)
+    assert slot(d, i, 0, 0) != slot(b, i, 0, 0)
+    # no-slip (-y) against pressure (+x): corner (2, 0), link (1, -1, 0)
+    i = dir_of((1, -1, 0))
+    assert slot(a, i, 2, 0) == slot(b, i, 2, 0)
+    # velocity (-x) against pressure (+y): corner (0, 2), link (-1, 1, 0)
+    a, _ = _corner_case((V, P, V, P, X, X), uw, q)
+    e, _ = _corner_case((V, P, X, X, X, X), uw, q)
+    i = dir_of((-1, 1, 0))
+    assert slot(a, i, 0, 2) == slot(e, i, 0, 2)
+    # two velocity faces (-x, -y): the lower face index (-x) decides
+    i = dir_of((-1, -1, 0))
+    assert slot(a, i, 0, 0) == slot(e, i, 0, 0)
+    h, _ = _corner_case((X, X, V, P, X, X), uw, q)
+    assert slot(a, i, 0, 0) != slot(h, i, 0, 0)
