@@ -1,21 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the fused stream-collide hot path on one MI355X.
 
-Headline workload: turbulent-channel-shaped flow, D3Q19 TRT with Guo
-forcing, 256x128x128 cells (x streamwise, y wall-normal), periodic in x and
-z, halfway bounce-back walls on the y faces, FP32 storage, laminar parabola
-(centre-line u = 0.05) plus seeded uniform +-5% velocity noise.  One step is
-one fused stream-collide kernel over every cell; the FP64 mass/momentum
-diagnostics run every 1000 steps inside the timed region.  The metric is
-MLUPS (million lattice-cell updates per second) and the fraction of the HBM
-roofline P_max = b_s / n_b of the paper (LAGOON scalability section, Eq. (3)),
-with n_b = 2 q s bytes per cell update (each population read once and
-written once, s bytes per population).
+Headline workload: obstacle flow, D3Q27 TRT, 384x384x384 cells, velocity
+inflow u = (0.04, 0, 0) at -x, pressure outflow rho = 1 at +x, periodic y and
+z faces, seeded random non-overlapping solid spheres (radius 6-20) filling
+10% of the volume as bounce-back cells, FP32 storage: the largest workload
+of the set that fits one GPU (6.1 GB of populations, far beyond the 256 MB
+last-level cache).  One step is one fused stream-collide kernel over every
+cell; the FP64 mass/momentum diagnostics run every 1000 steps inside the
+timed region.  The metric is MLUPS (million lattice-cell updates per second)
+and the fraction of the HBM roofline P_max = b_s / n_b of the paper (LAGOON
+scalability section, Eq. (3)), with n_b = 2 q s bytes per cell update (each
+population read once and written once, s bytes per population) plus one
+byte of solid flag.
 
 The JSON line on stdout also carries the other storage forms and
-workloads (FP16/BF16 deviation storage, D3Q27 obstacles, closures) as
-`forms`, the measured device copy bandwidth, and the oracle timed on the
-host cores (`cpu_baseline`).
+workloads (FP16/BF16 deviation storage, the channels, closures, MRT, the
+Esoteric Twist and sparse addressing) as `forms`, the measured device copy
+bandwidth, the paper's own CPU figures as context, and the FP64 oracle timed
+on the host cores (`cpu_baseline`).  The same oracle runs, on stated smaller
+copies of each workload, give the velocity L2 error of every form against
+FP64 (`velocity_l2_vs_oracle`).
 """
 from __future__ import annotations
 
@@ -68,8 +73,12 @@ def channel_cfg(nx, ny, nz, storage="f32", closure="none", collision="trt"):
 
 
 def obstacle_cfg(n=384, collision="trt"):
+    """D3Q27 obstacle flow on n^3 cells: velocity inflow 0.04 at -x, pressure
+    outflow at +x, periodic y and z, random spheres (radius 6-20) filling 10%,
+    seed 2024, sphere centres 32 cells from the x faces at n = 384 (scaled
+    with n for smaller copies: 11 cells at n = 128)."""
     from paper_2305_09910_amd import inputs
-    solid, _ = inputs.spheres(n, n, n, fill=0.10, x_margin=32, seed=2024)
+    solid, _ = inputs.spheres(n, n, n, fill=0.10, x_margin=round(32 * n / 384), seed=2024)
     uw = np.zeros((6, 3))
     uw[0] = (0.04, 0, 0)
     # ghost rates >= 1.5 keep the D3Q27 tensor-product MRT stable at low viscosity
@@ -104,7 +113,7 @@ KERNEL_SOURCES = ["paper_2305_09910_amd/csrc/lbm_kernels.hip", "paper_2305_09910
                   "paper_2305_09910_amd/csrc/lattice.h",
                   "paper_2305_09910_amd/csrc/stencil.h", "paper_2305_09910_amd/csrc/internal.h",
                   "paper_2305_09910_amd/csrc/mlp_wave.h"]
-PROFILE = "profiles/stream_collide_channel_256x128x128.md"
+PROFILE = "profiles/stream_collide_obstacles_384x384x384_d3q27.md"
 
 
 def kernel_source_hash():
@@ -137,22 +146,14 @@ def profiled_traffic():
 
 
 def make_lattice(cfg):
-    from paper_2305_09910_amd import inputs, lbm
+    from paper_2305_09910_amd import lbm
     lat = lbm.Lattice(cfg["shape"], q=cfg["q"], tau=cfg["tau"], force=cfg["force"], bc=cfg["bc"],
                       u_bc=cfg["u_bc"], solid=cfg["solid"], storage=cfg["storage"], closure=cfg["closure"],
                       collision=cfg.get("collision", "trt"), mrt_rates=cfg.get("mrt_rates"),
                       streaming=cfg.get("streaming", "aa"))
     if cfg["closure"] == "mlp":
         lat.set_closure_weights(demo_closure_weights())
-    nx, ny, nz = cfg["shape"]
-    if cfg["name"].startswith("channel"):
-        rho, u = inputs.channel(nx, ny, nz, 0.05, 0.05, seed=1234)
-    elif cfg["name"].startswith("porous"):
-        rho, u = inputs.uniform_flow(nx, ny, nz, (0.0, 0, 0))  # at rest; the force drives it
-    else:
-        rho, u = inputs.uniform_flow(nx, ny, nz, (0.04, 0, 0))
-        if cfg["solid"] is not None:
-            u[:, cfg["solid"] == 1] = 0.0
+    rho, u = initial_fields(cfg)
     lat.init_equilibrium(rho, u)
     return lat
 
@@ -232,41 +233,173 @@ def copy_bandwidth(nbytes=2 << 30, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(cfg, budget_s=12.0):
-    """The FP64 oracle on the host cores, on the first steps of the same workload."""
+# ---------------------------------------------------------------------------
+# FP64 oracle leg: the CPU baseline (the oracle timed on the host cores on a
+# bounded copy of the headline workload) and, from the same kind of oracle
+# runs on smaller copies of every workload, the velocity L2 error of each GPU
+# form against FP64.
+# ---------------------------------------------------------------------------
+# name -> (workload config at the copy size, steps); which forms use it below
+L2_REFS = {
+    "obstacles_128^3_d3q27": (lambda: obstacle_cfg(128), 200),
+    "channel_128x64x64": (lambda: channel_cfg(128, 64, 64), 1000),
+    "channel_64x32x32_smagorinsky": (lambda: channel_cfg(64, 32, 32, closure="smagorinsky"), 1000),
+    "channel_64x32x32_mlp_closure": (lambda: channel_cfg(64, 32, 32, closure="mlp"), 200),
+    "channel_64x32x32_mrt": (lambda: channel_cfg(64, 32, 32, collision="mrt"), 1000),
+    "obstacles_64^3_d3q27_mrt": (lambda: obstacle_cfg(64, collision="mrt"), 200),
+    "porous_64^3_d3q19": (lambda: porous_cfg(64), 500),
+}
+HEADLINE = "obstacles_384^3_d3q27_f32"
+CPU_BASELINE_REF = "obstacles_128^3_d3q27"
+
+
+def l2_ref_of(form):
+    """The oracle copy and GPU storage/streaming under which a form's velocity
+    L2 error is measured: the same workload, collision, closure, storage and
+    streaming scheme on a smaller copy (same recipe and seed)."""
+    if form.startswith("obstacles"):
+        return "obstacles_64^3_d3q27_mrt" if form.endswith("_mrt") else "obstacles_128^3_d3q27"
+    if form.startswith("porous"):
+        return "porous_64^3_d3q19"
+    if "smagorinsky" in form:
+        return "channel_64x32x32_smagorinsky"
+    if "mlp_closure" in form:
+        return "channel_64x32x32_mlp_closure"
+    if form.endswith("_mrt"):
+        return "channel_64x32x32_mrt"
+    return "channel_128x64x64"
+
+
+def run_oracle(cfg, steps):
+    """FP64 two-lattice oracle on one workload from the same initial fields
+    as the GPU run; returns (u [3][nz][ny][nx], seconds, threads)."""
     import oracle
     from paper_2305_09910_amd import inputs
-    nx, ny, nz = cfg["shape"]
-    rho, u = inputs.channel(nx, ny, nz, 0.05, 0.05, seed=1234)
-    o = oracle.Sim(cfg["q"], cfg["shape"], bc=(0, 0, 1, 1, 0, 0), tau=cfg["tau"], force=cfg["force"])
+    bcs = {"periodic": oracle.BC_PERIODIC, "noslip": oracle.BC_NOSLIP, "velocity": oracle.BC_VELOCITY,
+           "pressure": oracle.BC_PRESSURE}
+    cl = {"none": oracle.CL_NONE, "smagorinsky": oracle.CL_SMAG, "mlp": oracle.CL_MLP}[cfg["closure"]]
+    o = oracle.Sim(cfg["q"], cfg["shape"], bc=tuple(bcs[b] for b in cfg["bc"]), tau=cfg["tau"], force=cfg["force"],
+                   u_bc=cfg["u_bc"], solid=cfg["solid"], closure=cl, cs=0.1)
+    if cfg.get("collision") == "mrt":
+        o.set_mrt(cfg["mrt_rates"] if cfg["q"] == 27 else oracle.MRT_DHUMIERES)
+    if cl == oracle.CL_MLP:
+        w = demo_closure_weights().astype(np.float64)
+        o.set_mlp(w[:1313], w[1313:])
+    rho, u = initial_fields(cfg)
     o.init_equilibrium(rho, u)
-    o.step(1)  # first touch of both lattices
-    steps = 0
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        o.step(2)
-        steps += 2
+    o.step(steps)
     dt = time.perf_counter() - t0
+    _, uo = o.moments()
+    return uo, dt
+
+
+def initial_fields(cfg):
+    from paper_2305_09910_amd import inputs
+    nx, ny, nz = cfg["shape"]
+    if cfg["name"].startswith("channel"):
+        return inputs.channel(nx, ny, nz, 0.05, 0.05, seed=1234)
+    if cfg["name"].startswith("porous"):
+        return inputs.uniform_flow(nx, ny, nz, (0.0, 0, 0))
+    rho, u = inputs.uniform_flow(nx, ny, nz, (0.04, 0, 0))
+    if cfg["solid"] is not None:
+        u[:, cfg["solid"] == 1] = 0.0
+    return rho, u
+
+
+def velocity_l2(u_gpu, u_orc, solid=None):
+    """||u_gpu - u_orc||_2 / ||u_orc||_2 over the fluid cells, in FP64."""
+    a = np.asarray(u_gpu, dtype=np.float64).reshape(3, -1)
+    b = np.asarray(u_orc, dtype=np.float64).reshape(3, -1)
+    if solid is not None:
+        keep = np.asarray(solid).reshape(-1) == 0
+        a, b = a[:, keep], b[:, keep]
+    return float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+
+
+def oracle_leg(forms):
+    """The oracle on the host cores: the CPU baseline, and the references for
+    the velocity L2 error of every form (GPU run of the same copy, its
+    storage, streaming, collision and closure, against the oracle's FP64)."""
+    need = sorted({l2_ref_of(f) for f in forms} | {CPU_BASELINE_REF})
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nx * ny * nz * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{cfg['name']} D3Q19 FP64 two-lattice oracle, {steps} steps after 1 warm-up step "
-                      f"({dt:.1f} s, OpenMP over z)"}
+    refs, cpu = {}, None
+    for name in need:
+        mk, steps = L2_REFS[name]
+        cfg = mk()
+        log(f"[bench] oracle {name}, {steps} steps")
+        uo, dt = run_oracle(cfg, steps)
+        refs[name] = (cfg, steps, uo)
+        n = cfg["shape"][0] * cfg["shape"][1] * cfg["shape"][2]
+        log(f"[bench]   {n * steps / dt / 1e6:.1f} MLUPS, {dt:.1f} s")
+        if name == CPU_BASELINE_REF:
+            cpu = {"value": round(n * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+                   "sample": f"{name} (the 128^3 copy of the headline obstacle flow: same recipe, seed and "
+                             f"parameters), D3Q27 FP64 two-lattice oracle, {steps} steps from the initial state, "
+                             f"{dt:.1f} s, OpenMP over z on {cores} threads",
+                   "cpu_model": cpu_model()}
+    return cpu, refs
 
 
-FORMS = ["channel_512x256x256_f32", "channel_512x256x256_f16", "channel_512x256x256_bf16",
-         "obstacles_384^3_d3q27_f32", "channel_256x128x128_smagorinsky", "channel_256x128x128_mlp_closure",
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def gpu_l2(form, refs):
+    """Velocity L2 error of a form: the GPU run of the form's copy against the
+    oracle's FP64 run of the same copy."""
+    from paper_2305_09910_amd import lbm
+    name = l2_ref_of(form)
+    cfg, steps, uo = refs[name]
+    fcfg = form_cfg(form, sized=False)
+    cfg = dict(cfg, storage=fcfg["storage"], streaming=fcfg.get("streaming", "aa"))
+    lat = make_lattice(cfg)
+    lat.step(steps)
+    _, ug = lat.moments()
+    err = velocity_l2(ug.cpu().numpy(), uo, cfg["solid"])
+    del lat
+    return {"value": float(f"{err:.3g}"), "copy": name, "steps": steps, "storage": cfg["storage"],
+            "streaming": cfg["streaming"]}
+
+
+PAPER_CONTEXT = {
+    "kernel_mlups_per_node": 874, "roofline_mlups_per_node": 977, "bandwidth_gbs": 297.9, "bytes_per_cell": 304,
+    "hardware": "one HAWK node, 2x AMD EPYC 7742 (128 cores), STREAM bandwidth",
+    "workload": "D3Q19 MRT, FP64, Esoteric Twist in place, SoA, generated C kernels (LAGOON blocks of 24^3)",
+    "source": "Section 5.2, Eq. (3)",
+    "note": "another machine and precision: context, not the target",
+}
+
+FORMS = ["channel_256x128x128_f32", "channel_512x256x256_f32", "channel_512x256x256_f16",
+         "channel_512x256x256_bf16", "channel_256x128x128_smagorinsky", "channel_256x128x128_mlp_closure",
          "channel_512x256x256_mlp_closure", "channel_512x256x256_mrt", "obstacles_384^3_d3q27_mrt",
          "channel_256x128x128_et", "channel_512x256x256_f32_et", "channel_512x256x256_f16_et",
          "obstacles_384^3_d3q27_et", "porous_256^3_d3q19_f32", "porous_256^3_d3q19_f32_sparse",
          "porous_256^3_d3q19_f16", "porous_256^3_d3q19_f16_sparse", "channel_256x128x128_mlp_closure_et"]
 
+NOTES = {
+    "channel_256x128x128_f32": "319 MB of populations, partly resident in the 256 MB last-level cache: "
+                               "cache-assisted, not an HBM roofline figure",
+    "channel_256x128x128_smagorinsky": "cache-assisted (319 MB state)",
+    "channel_256x128x128_mlp_closure": "cache-assisted (319 MB state); bound by the vector ALU",
+    "channel_256x128x128_et": "cache-assisted (319 MB state)",
+    "channel_256x128x128_mlp_closure_et": "cache-assisted (319 MB state)",
+}
 
-def form_cfg(key):
-    return {
+
+def form_cfg(key, sized=True):
+    table = {
+        HEADLINE: lambda: obstacle_cfg(),
+        "channel_256x128x128_f32": lambda: channel_cfg(256, 128, 128, "f32"),
         "channel_512x256x256_f32": lambda: channel_cfg(512, 256, 256, "f32"),
         "channel_512x256x256_f16": lambda: channel_cfg(512, 256, 256, "f16"),
         "channel_512x256x256_bf16": lambda: channel_cfg(512, 256, 256, "bf16"),
-        "obstacles_384^3_d3q27_f32": lambda: obstacle_cfg(),
         "channel_256x128x128_smagorinsky": lambda: channel_cfg(256, 128, 128, "f32", "smagorinsky"),
         "channel_256x128x128_mlp_closure": lambda: channel_cfg(256, 128, 128, "f32", "mlp"),
         "channel_512x256x256_mlp_closure": lambda: channel_cfg(512, 256, 256, "f32", "mlp"),
@@ -280,8 +413,15 @@ def form_cfg(key):
         "porous_256^3_d3q19_f32_sparse": lambda: porous_cfg(256, "f32", "sparse"),
         "porous_256^3_d3q19_f16": lambda: porous_cfg(256, "f16"),
         "porous_256^3_d3q19_f16_sparse": lambda: porous_cfg(256, "f16", "sparse"),
-        "channel_256x128x128_mlp_closure_et": lambda: dict(channel_cfg(256, 128, 128, "f32", "mlp"), streaming="et"),
-    }[key]()
+        "channel_256x128x128_mlp_closure_et": lambda: dict(channel_cfg(256, 128, 128, "f32", "mlp"),
+                                                           streaming="et"),
+    }
+    if sized:
+        return table[key]()
+    # storage and streaming only (no full-size geometry): for the L2 copies
+    st = "f16" if "_f16" in key else ("bf16" if "_bf16" in key else "f32")
+    streaming = "et" if key.endswith("_et") else ("sparse" if key.endswith("_sparse") else "aa")
+    return {"storage": st, "streaming": streaming}
 
 
 def form_plan():
@@ -292,14 +432,15 @@ def form_plan():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and velocity L2 errors)")
     ap.add_argument("--no-forms", action="store_true", help="headline workload only")
     ap.add_argument("--form-steps", type=int, default=300)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB once with the library's copy kernel (counter calibration)")
-    ap.add_argument("--only-form", choices=FORMS, default=None,
+    ap.add_argument("--only-form", choices=[HEADLINE] + FORMS, default=None,
                     help="time only this form for --form-steps steps (for profiling); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -330,8 +471,8 @@ def main():
             f"kernel {fr['kernel_ms'] * 1e3:.1f} us")
         return
 
-    head = channel_cfg(256, 128, 128)
-    log(f"[bench] headline {head['name']} f32, warmup {args.warmup}, steps {args.steps}")
+    head = form_cfg(HEADLINE)
+    log(f"[bench] headline {HEADLINE}, warmup {args.warmup}, steps {args.steps}")
     r = time_lattice(head, args.steps, args.warmup)
     log(f"[bench] headline: {r['mlups']:.0f} MLUPS, kernel {r['kernel_ms']*1e3:.1f} us, "
         f"{r['achieved_gbs']:.0f} GB/s ({100*r['roofline_frac']:.1f}% of 8 TB/s)")
@@ -351,15 +492,24 @@ def main():
                           "achieved_gbs": round(fr["achieved_gbs"], 1),
                           "roofline_frac": round(fr["roofline_frac"], 4),
                           "frac_of_copy": round(fr["achieved_gbs"] / bs, 4) if bs else None}
+            if key in NOTES:
+                forms[key]["note"] = NOTES[key]
             log(f"[bench]   {forms[key]}")
 
-    cpu = None
+    cpu, l2 = None, {}
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle on host cores)")
-        cpu = cpu_baseline(head)
+        log("[bench] oracle leg: cpu baseline and velocity L2 references (oracle on host cores)")
+        cpu, refs = oracle_leg([HEADLINE] + list(forms))
         log(f"[bench]   {cpu}")
+        for key in [HEADLINE] + list(forms):
+            l2[key] = gpu_l2(key, refs)
+            log(f"[bench]   velocity L2 {key}: {l2[key]}")
+            if key in forms:
+                forms[key]["velocity_l2_vs_oracle"] = l2[key]
+        torch.cuda.empty_cache()
 
     traffic = profiled_traffic()
+    algo = r["bytes_per_cell"] * r["cells"]
     out = {
         "metric": "MLUPS and % HBM roofline, FP32 vs FP16-storage vs learned-closure",
         "value": round(r["mlups"], 1),
@@ -373,17 +523,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "channel 256x128x128 D3Q19 TRT+Guo, y no-slip walls, x/z periodic, FP32 storage",
-                   "cells": r["cells"], "stencil": "D3Q19", "storage": "f32", "tau": head["tau"],
-                   "force_x": head["force"][0], "diagnostics_every": 1000},
+        "config": {"workload": "obstacle flow 384x384x384 D3Q27 TRT, velocity inflow 0.04 at -x, pressure "
+                               "outflow at +x, periodic y/z, seeded solid spheres (radius 6-20) filling 10%, "
+                               "FP32 storage",
+                   "cells": r["cells"], "fluid_cells": r["fluid_cells"], "stencil": "D3Q27", "storage": "f32",
+                   "tau": head["tau"], "diagnostics_every": 1000, "mflups": round(r["mflups"], 1)},
         "roofline": {"bound": "hbm", "achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(r["roofline_frac"], 4),
                      "traffic": (round(traffic / 1e6, 1) if traffic else None),
                      "traffic_unit": "MB per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, copy-calibrated)",
-                     "algorithmic_mb_per_launch": round(r["bytes_per_cell"] * r["cells"] / 1e6, 1),
-                     "kernel": "k_stream_collide<19,f32,none> (one launch per step)",
-                     "bytes_per_cell": r["bytes_per_cell"], "kernel_us": round(r["kernel_ms"] * 1e3, 2)},
+                     "algorithmic_mb_per_launch": round(algo / 1e6, 1),
+                     "kernel": "k_stream_collide<27,f32,none,mask,TRT> (one launch per step)",
+                     "bytes_per_cell": r["bytes_per_cell"], "kernel_us": round(r["kernel_ms"] * 1e3, 2),
+                     "frac_of_copy": round(r["achieved_gbs"] / bs, 4) if bs else None},
+        "velocity_l2_vs_oracle": l2.get(HEADLINE),
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
         "copy_bandwidth_gbs": round(bs, 1) if bs else None,
         "forms": forms,
     }
