@@ -80,6 +80,10 @@ def lib():
         L.orc_set_mrt.argtypes = [ctypes.c_void_p, _D]
         L.orc_collide_mrt.argtypes = [ctypes.c_int, _D, ctypes.c_double, _D, _D, ctypes.c_int, ctypes.c_double, _D,
                                       _D]
+        L.orc_set_hrr.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.orc_hrr_norms.argtypes = [_D]
+        L.orc_collide_hrr.argtypes = [_D, ctypes.c_double, ctypes.c_double, _D, _D, _D]
+        L.orc_fd_gradient.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         L.orc_moments.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_totals.argtypes = [ctypes.c_void_p, _D, _D]
@@ -150,6 +154,24 @@ def collide_mrt(q, f, tau, rates=MRT_DHUMIERES, F=(0.0, 0.0, 0.0), closure=CL_NO
     if lib().orc_collide_mrt(q, _d(f), float(tau), _d(r), _d(F), int(closure), float(cs), _d(out), _d(tu)) != 0:
         raise ValueError("singular MRT basis")
     return out, float(tu[0])
+
+
+def hrr_norms() -> np.ndarray:
+    """Lattice norms of the six D3Q19 third-order Hermite combinations."""
+    out = np.zeros(6)
+    lib().orc_hrr_norms(_d(out))
+    return out
+
+
+def collide_hrr(f, tau, sigma, F=(0.0, 0.0, 0.0), grad=None) -> np.ndarray:
+    """One D3Q19 HRR collision of a single cell; grad[3][3] = d u_a / d x_b
+    of the velocity field (zero if None)."""
+    f = _f64(f)
+    F = _f64(F)
+    G = _f64(np.zeros((3, 3)) if grad is None else grad).reshape(9)
+    out = np.zeros(19)
+    lib().orc_collide_hrr(_d(f), float(tau), float(sigma), _d(F), _d(G), _d(out))
+    return out
 
 
 def noneq_flux(q, f, F=(0.0, 0.0, 0.0)) -> np.ndarray:
@@ -257,6 +279,21 @@ class Sim:
     def set_mrt(self, rates=MRT_DHUMIERES):
         if lib().orc_set_mrt(self._h, _d(_f64(rates))) != 0:
             raise ValueError("singular MRT basis")
+
+    def set_hrr(self, sigma=0.995):
+        """Hybrid recursive regularised collision (D3Q19); sigma is the weight
+        of the projected non-equilibrium flux against the finite-difference one."""
+        if lib().orc_set_hrr(self._h, float(sigma)) != 0:
+            raise ValueError("HRR needs D3Q19 and sigma in [0, 1]")
+
+    def fd_gradient(self, u):
+        """Velocity gradient [3, 3, nz, ny, nx] (d u_a / d x_b) of a field u [3, nz, ny, nx]
+        with the HRR finite-difference rules at walls, solids and faces."""
+        nx, ny, nz = self.shape
+        u = _f64(u).reshape(3, -1)
+        out = np.zeros((3, 3, nz, ny, nx))
+        lib().orc_fd_gradient(self._h, _d(u), _d(out))
+        return out
 
     def set_mlp(self, params, norm):
         lib().orc_set_mlp(self._h, _d(_f64(params)), _d(_f64(norm)))

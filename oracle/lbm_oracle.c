@@ -398,6 +398,111 @@ void orc_features(const double *P, double rho, double tau, double cs, double *xo
 }
 
 /* ------------------------------------------------------------------------ */
+/* Hybrid recursive regularisation (HRR; Jacob, Malaspinas & Sagaut 2018:    */
+/* the "D3Q19HRR" collision of the LaBS section).  D3Q19 only.               */
+/* The post-collision state is rebuilt from Hermite coefficients:            */
+/*   f*_i = feq_i + (1 - 1/tau) f1_i + S_i / 2,                              */
+/*   f1_i = w_i [ H2_i : Pi / (2 c_s^4) + sum_k T_k(c_i) A_k / N_k ],        */
+/* the regularised form of g = f - feq + S/2 (BGK with Guo forcing written   */
+/* as feq + (1 - 1/tau) g + S/2; g has no first moment, so the collision     */
+/* keeps mass and adds exactly F to the momentum).  Pi = sigma Pi_PR +       */
+/* (1 - sigma) Pi_FD blends the projected flux of g,                         */
+/* Pi_PR = sum c c (f - feq) + (uF + Fu)/2, with the                         */
+/* finite-difference one Pi_FD = -2 rho c_s^2 tau S (S the strain rate of    */
+/* the velocity field), and the third-order coefficients follow by the       */
+/* recursion a3_abg = u_a Pi_bg + u_b Pi_ag + u_g Pi_ab.  D3Q19 carries the   */
+/* mixed third-order Hermite polynomials H_aab only as the six sums and      */
+/* differences T_k (H_xxy +- H_yzz, H_xzz +- H_xyy, H_yyz +- H_xxz), which   */
+/* are orthogonal with the lattice weights; A_k is the matching combination  */
+/* of a3, and N_k = sum_i w_i T_k(c_i)^2 its lattice norm (the projection     */
+/* reproduces the moment A_k exactly).  The equilibrium adds the same        */
+/* third-order terms with a3 = rho u u u.                                    */
+/* Pinned by conservation, the BGK limit (sigma = 1, u = 0, second-order     */
+/* non-equilibrium), the removal of the fourth-order moments, the Taylor-    */
+/* Green rate and the convergence of the Poiseuille profile (tests).         */
+/* ------------------------------------------------------------------------ */
+static double hermite3(const int *c, int a, int b, int g)
+{
+    const double cs2 = 1.0 / 3.0;
+    return c[a] * c[b] * c[g] - cs2 * (c[a] * (b == g) + c[b] * (a == g) + c[g] * (a == b));
+}
+
+/* T_k(c) for k = 0..5 */
+static void t3_values(const int *c, double *T)
+{
+    enum { X = 0, Y = 1, Z = 2 };
+    double xxy = hermite3(c, X, X, Y), yzz = hermite3(c, Y, Z, Z);
+    double xzz = hermite3(c, X, Z, Z), xyy = hermite3(c, X, Y, Y);
+    double yyz = hermite3(c, Y, Y, Z), xxz = hermite3(c, X, X, Z);
+    T[0] = xxy + yzz;
+    T[1] = xxy - yzz;
+    T[2] = xzz + xyy;
+    T[3] = xzz - xyy;
+    T[4] = yyz + xxz;
+    T[5] = yyz - xxz;
+}
+
+/* The combinations A_k of a symmetric third-order tensor given by its six  */
+/* mixed components a_xxy, a_yzz, a_xzz, a_xyy, a_yyz, a_xxz.               */
+static void t3_combos(double xxy, double yzz, double xzz, double xyy, double yyz, double xxz, double *A)
+{
+    A[0] = xxy + yzz;
+    A[1] = xxy - yzz;
+    A[2] = xzz + xyy;
+    A[3] = xzz - xyy;
+    A[4] = yyz + xxz;
+    A[5] = yyz - xxz;
+}
+
+/* Third-order terms of the HRR equilibrium, added to feq (a3 = rho u u u). */
+static void hrr_equilibrium3(int q, double rho, const double *u, const double *norm, double *feq)
+{
+    double A[6], T[6];
+    double x = u[0], y = u[1], z = u[2];
+    t3_combos(rho * x * x * y, rho * y * z * z, rho * x * z * z, rho * x * y * y, rho * y * y * z, rho * x * x * z, A);
+    for (int i = 0; i < q; ++i) {
+        t3_values(VEL[i], T);
+        double acc = 0.0;
+        for (int k = 0; k < 6; ++k) acc += T[k] * A[k] / norm[k];
+        feq[i] += weight(q, i) * acc;
+    }
+}
+
+/* Regularised non-equilibrium f1 from the blended flux Pi[3][3] and u.     */
+static void hrr_f1(int q, const double Pi[3][3], const double *u, const double *norm, double *f1)
+{
+    const double cs2 = 1.0 / 3.0;
+    double a3[3][3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int g = 0; g < 3; ++g) a3[a][b][g] = u[a] * Pi[b][g] + u[b] * Pi[a][g] + u[g] * Pi[a][b];
+    double A[6], T[6];
+    t3_combos(a3[0][0][1], a3[1][2][2], a3[0][2][2], a3[0][1][1], a3[1][1][2], a3[0][0][2], A);
+    for (int i = 0; i < q; ++i) {
+        double h2 = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) h2 += (VEL[i][a] * VEL[i][b] - cs2 * (a == b)) * Pi[a][b];
+        t3_values(VEL[i], T);
+        double t3 = 0.0;
+        for (int k = 0; k < 6; ++k) t3 += T[k] * A[k] / norm[k];
+        f1[i] = weight(q, i) * (h2 / (2.0 * cs2 * cs2) + t3);
+    }
+}
+
+/* Lattice norms N_k of the D3Q19 third-order combinations (2/27 for the     */
+/* sums, 6/27 for the differences; pinned in the tests).                    */
+int orc_hrr_norms(double *norm)
+{
+    double T[6];
+    for (int k = 0; k < 6; ++k) norm[k] = 0.0;
+    for (int i = 0; i < 19; ++i) {
+        t3_values(VEL[i], T);
+        for (int k = 0; k < 6; ++k) norm[k] += weight(19, i) * T[k] * T[k];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Simulation state.                                                         */
 /* ------------------------------------------------------------------------ */
 enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
@@ -413,14 +518,19 @@ typedef struct {
     double cs;
     double mlp[MLP_NPARAM];
     double norm[MLP_NNORM];
-    int collision;        /* 0 TRT, 1 MRT */
+    int collision;        /* 0 TRT, 1 MRT, 2 HRR */
     double mrt_rates[5];  /* ghost rates: energy, energy square, q, pi, m */
+    double hrr_sigma;     /* HRR: weight of the projected flux (1 - weight of the FD one) */
+    double t3norm[6];     /* HRR: lattice norms sum_i w_i T_k(c_i)^2 of the third-order combinations */
+    double *uprev;        /* HRR: [3][n] velocity field of the previous step (the FD gradient's input) */
     double Mm[27 * 27], Minv[27 * 27];
     int mgroup[27];
     unsigned char *solid; /* NULL: all fluid */
     double *f, *g;        /* [q][n] canonical (post-stream, pre-collide) and scratch */
     int64_t fallbacks;    /* cells where the MLP closure fell back to Smagorinsky */
 } orc_sim;
+
+static void hrr_update_velocity(orc_sim *s);
 
 static int64_t cell_index(const orc_sim *s, int x, int y, int z)
 {
@@ -477,6 +587,7 @@ void orc_destroy(orc_sim *s)
 {
     if (!s) return;
     free(s->solid);
+    free(s->uprev);
     free(s->f);
     free(s->g);
     free(s);
@@ -513,12 +624,14 @@ void orc_init_equilibrium(orc_sim *s, const double *rho, const double *u)
         orc_equilibrium(s->q, rho[c], uc, feq);
         for (int i = 0; i < s->q; ++i) s->f[i * s->n + c] = is_solid(s, c) ? 0.0 : feq[i];
     }
+    hrr_update_velocity(s);
 }
 
 void orc_set_pdfs(orc_sim *s, const double *f)
 {
     ensure_lattices(s);
     memcpy(s->f, f, sizeof(double) * s->q * s->n);
+    hrr_update_velocity(s);
 }
 
 void orc_get_pdfs(orc_sim *s, double *f)
@@ -537,8 +650,8 @@ void orc_get_pdfs(orc_sim *s, double *f)
  * Pinned by: mass and momentum invariants, the BGK special case, the exact
  * Poiseuille profile and the Taylor-Green decay rate (tests).
  */
-static void collide_cell(const orc_sim *s, const double *f, double *fstar, double *u_out, double *tau_out,
-                         int64_t *fallback)
+static void collide_cell(const orc_sim *s, const double *f, const double (*grad)[3], double *fstar, double *u_out,
+                         double *tau_out, int64_t *fallback)
 {
     int q = s->q;
     double rho = 0.0, j[3] = {0, 0, 0};
@@ -586,6 +699,26 @@ static void collide_cell(const orc_sim *s, const double *f, double *fstar, doubl
                 if (fallback) ++*fallback;
             }
         }
+    }
+    if (s->collision == 2) {
+        /* HRR: grad[a][b] = d u_a / d x_b of the velocity field (FD part). */
+        hrr_equilibrium3(q, rho, u, s->t3norm, feq);
+        double Pi[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double acc = 0.0;
+                for (int i = 0; i < q; ++i) acc += VEL[i][a] * VEL[i][b] * (f[i] - feq[i]);
+                double pr = acc + 0.5 * (u[a] * s->F[b] + s->F[a] * u[b]);
+                double fd = grad ? -(1.0 / 3.0) * rho * tau * (grad[a][b] + grad[b][a]) : pr;
+                Pi[a][b] = s->hrr_sigma * pr + (1.0 - s->hrr_sigma) * fd;
+            }
+        double f1[27];
+        hrr_f1(q, Pi, u, s->t3norm, f1);
+        for (int i = 0; i < q; ++i) fstar[i] = feq[i] + (1.0 - 1.0 / tau) * f1[i] + 0.5 * S[i];
+        if (u_out)
+            for (int a = 0; a < 3; ++a) u_out[a] = u[a];
+        if (tau_out) *tau_out = tau;
+        return;
     }
     if (s->collision == 1) {
         /* m_neq = M (f - feq), mS = M S; each moment a changes by           */
@@ -638,7 +771,7 @@ void orc_collide(int q, const double *f, double tau, double magic, const double 
     for (int a = 0; a < 3; ++a) s.F[a] = F[a];
     s.closure = closure;
     s.cs = cs;
-    collide_cell(&s, f, fstar, 0, tau_used, 0);
+    collide_cell(&s, f, 0, fstar, 0, tau_used, 0);
 }
 
 /* Collide a single cell with the MRT operator (rates as orc_set_mrt).     */
@@ -654,7 +787,7 @@ int orc_collide_mrt(int q, const double *f, double tau, const double *rates, con
     s.closure = closure;
     s.cs = cs;
     if (orc_set_mrt(&s, rates) != 0) return -1;
-    collide_cell(&s, f, fstar, 0, tau_used, 0);
+    collide_cell(&s, f, 0, fstar, 0, tau_used, 0);
     return 0;
 }
 
@@ -733,6 +866,140 @@ static double push_target(const orc_sim *s, int x, int y, int z, int i, double v
 }
 
 /*
+ * Neighbour of (x,y,z) one cell along axis b in direction dir (+1 or -1),
+ * for the finite-difference velocity gradient of HRR:
+ *   0  a cell of the domain (fluid; *nb its index, wrapped on periodic axes),
+ *   1  a wall half a cell away with velocity uw: a no-slip face (0), a
+ *      velocity face (its u_bc) or a solid cell (0),
+ *   2  a pressure face: the ghost outside carries the cell's own velocity.
+ */
+static int fd_neighbour(const orc_sim *s, int x, int y, int z, int b, int dir, int64_t *nb, double *uw)
+{
+    int p[3] = {x, y, z};
+    int ext[3] = {s->nx, s->ny, s->nz};
+    p[b] += dir;
+    if (p[b] < 0 || p[b] >= ext[b]) {
+        int face = 2 * b + (dir > 0);
+        if (s->bc[face] == BC_PERIODIC) {
+            p[b] = (p[b] + ext[b]) % ext[b];
+        } else if (s->bc[face] == BC_PRESSURE) {
+            return 2;
+        } else {
+            for (int a = 0; a < 3; ++a) uw[a] = s->bc[face] == BC_VELOCITY ? s->ubc[face][a] : 0.0;
+            return 1;
+        }
+    }
+    int64_t c = cell_index(s, p[0], p[1], p[2]);
+    if (is_solid(s, c)) {
+        for (int a = 0; a < 3; ++a) uw[a] = 0.0;
+        return 1;
+    }
+    *nb = c;
+    return 0;
+}
+
+/*
+ * Velocity gradient G[a][b] = d u_a / d x_b of the field uf [3][n] at a
+ * fluid cell: central differences between two domain neighbours; next to a
+ * wall (half a cell away, velocity uw) the derivative of the quadratic
+ * through the wall point and the two nearest cells, -4/3 uw + u0 + u1/3
+ * (mirrored on the + side); between two walls (uw+ - uw-); a pressure-face
+ * ghost takes the cell's own value.  Pinned by exactness on linear and
+ * quadratic fields (tests).
+ */
+static void fd_gradient(const orc_sim *s, const double *uf, int x, int y, int z, double G[3][3])
+{
+    int64_t N = s->n, c0 = cell_index(s, x, y, z);
+    for (int b = 0; b < 3; ++b) {
+        int64_t im = -1, ip = -1;
+        double wm[3] = {0, 0, 0}, wp[3] = {0, 0, 0};
+        int km = fd_neighbour(s, x, y, z, b, -1, &im, wm);
+        int kp = fd_neighbour(s, x, y, z, b, +1, &ip, wp);
+        for (int a = 0; a < 3; ++a) {
+            double u0 = uf[a * N + c0];
+            double um = km == 0 ? uf[a * N + im] : u0;
+            double up = kp == 0 ? uf[a * N + ip] : u0;
+            double d;
+            if (km == 1 && kp == 1)
+                d = wp[a] - wm[a];
+            else if (km == 1)
+                d = -(4.0 / 3.0) * wm[a] + u0 + up / 3.0;
+            else if (kp == 1)
+                d = (4.0 / 3.0) * wp[a] - u0 - um / 3.0;
+            else
+                d = 0.5 * (up - um);
+            G[a][b] = d;
+        }
+    }
+}
+
+/* Gradient of a velocity field at every cell (for the tests): G [9][n],    */
+/* row 3a + b = d u_a / d x_b; solid cells get zeros.                       */
+void orc_fd_gradient(const orc_sim *s, const double *uf, double *G)
+{
+    int64_t N = s->n;
+    for (int z = 0; z < s->nz; ++z)
+        for (int y = 0; y < s->ny; ++y)
+            for (int x = 0; x < s->nx; ++x) {
+                int64_t c = cell_index(s, x, y, z);
+                double g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+                if (!is_solid(s, c)) fd_gradient(s, uf, x, y, z, g);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) G[(3 * a + b) * N + c] = g[a][b];
+            }
+}
+
+/* HRR state: the velocity field u = (j + F/2)/rho of the current populations */
+/* (zero at solid cells), the FD gradient's input on the next step.          */
+static void hrr_update_velocity(orc_sim *s)
+{
+    if (s->collision != 2 || !s->uprev || !s->f) return;
+    int64_t N = s->n;
+    for (int64_t c = 0; c < N; ++c) {
+        double r = 0.0, j[3] = {0, 0, 0};
+        for (int i = 0; i < s->q; ++i) {
+            double v = s->f[i * N + c];
+            r += v;
+            for (int a = 0; a < 3; ++a) j[a] += VEL[i][a] * v;
+        }
+        for (int a = 0; a < 3; ++a) s->uprev[a * N + c] = is_solid(s, c) ? 0.0 : (j[a] + 0.5 * s->F[a]) / r;
+    }
+}
+
+/* Select the HRR collision (D3Q19 only) with the weight sigma in [0, 1] of */
+/* the projected flux.  Returns -1 for another stencil or sigma outside.    */
+int orc_set_hrr(orc_sim *s, double sigma)
+{
+    if (s->q != 19 || !(sigma >= 0.0 && sigma <= 1.0)) return -1;
+    s->collision = 2;
+    s->hrr_sigma = sigma;
+    orc_hrr_norms(s->t3norm);
+    if (!s->uprev) s->uprev = (double *)calloc((size_t)(3 * s->n), sizeof(double));
+    hrr_update_velocity(s);
+    return 0;
+}
+
+/* One HRR collision of a single cell with a given velocity gradient       */
+/* grad[3][3] (row a: d u_a / d x_b), for the invariant tests.             */
+void orc_collide_hrr(const double *f, double tau, double sigma, const double *F, const double *grad,
+                     double *fstar)
+{
+    orc_sim s;
+    memset(&s, 0, sizeof s);
+    s.q = 19;
+    s.tau = tau;
+    s.magic = 0.25;
+    for (int a = 0; a < 3; ++a) s.F[a] = F[a];
+    s.collision = 2;
+    s.hrr_sigma = sigma;
+    orc_hrr_norms(s.t3norm);
+    double G[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) G[a][b] = grad[3 * a + b];
+    collide_cell(&s, f, (const double(*)[3])G, fstar, 0, 0, 0);
+}
+
+/*
  * Advance n time steps: for every fluid cell collide (Eq. 1) and push every
  * population to its destination (Eq. 2) in a second lattice, then swap.
  * Pinned by Poiseuille, Taylor-Green, conservation, symmetry and plug-flow
@@ -743,6 +1010,9 @@ void orc_step(orc_sim *s, int64_t nsteps)
     ensure_lattices(s);
     int q = s->q;
     int64_t N = s->n;
+    /* HRR: the gradient of this step uses the velocity field of the previous */
+    /* step (uprev); the velocities of this step go to unext                   */
+    double *unext = s->collision == 2 ? (double *)calloc((size_t)(3 * N), sizeof(double)) : 0;
     for (int64_t t = 0; t < nsteps; ++t) {
         int64_t fb = 0;
 #pragma omp parallel for schedule(static) reduction(+ : fb)
@@ -751,9 +1021,12 @@ void orc_step(orc_sim *s, int64_t nsteps)
                 for (int x = 0; x < s->nx; ++x) {
                     int64_t c = cell_index(s, x, y, z);
                     if (is_solid(s, c)) continue;
-                    double f[27], fs[27], u[3];
+                    double f[27], fs[27], u[3], G[3][3];
                     for (int i = 0; i < q; ++i) f[i] = s->f[i * N + c];
-                    collide_cell(s, f, fs, u, 0, &fb);
+                    if (unext) fd_gradient(s, s->uprev, x, y, z, G);
+                    collide_cell(s, f, unext ? (const double(*)[3])G : 0, fs, u, 0, &fb);
+                    if (unext)
+                        for (int a = 0; a < 3; ++a) unext[a * N + c] = u[a];
                     for (int i = 0; i < q; ++i) {
                         int64_t tgt;
                         int d;
@@ -765,7 +1038,13 @@ void orc_step(orc_sim *s, int64_t nsteps)
         double *tmp = s->f;
         s->f = s->g;
         s->g = tmp;
+        if (unext) {
+            tmp = s->uprev;
+            s->uprev = unext;
+            unext = tmp;
+        }
     }
+    free(unext);
 }
 
 /* Density and velocity u = (j + F/2)/rho of the canonical state; u [3][n]. */
@@ -821,7 +1100,7 @@ static void probe_post(const orc_sim *s, const double *rho, const double *u, int
 {
     double f[27];
     probe_rec(s, rho, u, x, y, z, k, f);
-    collide_cell(s, f, fs, uc, 0, 0);
+    collide_cell(s, f, 0, fs, uc, 0, 0);
 }
 
 static void probe_rec(const orc_sim *s, const double *rho, const double *u, int x, int y, int z, int k,
@@ -862,6 +1141,10 @@ static void probe_rec(const orc_sim *s, const double *rho, const double *u, int 
 void orc_probe(const orc_sim *s, const double *rho, const double *u, int k, int64_t ncell, const int64_t *cells,
                double *out)
 {
+    if (s->collision == 2) { /* HRR's gradient depends on the step history: no probe */
+        for (int64_t r = 0; r < ncell * s->q; ++r) out[r] = NAN;
+        return;
+    }
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t r = 0; r < ncell; ++r) {
         int64_t c = cells[r];
