@@ -295,6 +295,19 @@ size_t lbm_mlp_work_bytes(int64_t n);
 int lbm_mlp_loss_grad(const float *params_dev, const float *x_dev, const float *t_dev, int64_t n, float *grad_dev,
                       float *loss_dev, void *work_dev, void *stream);
 
+/* Allocation-free variant of lbm_mlp_loss_grad, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops,
+ * harnesses that forbid allocation): the same kernels and the same results
+ * bit for bit, with the per-block partial gradients in a static device array
+ * of the library instead of work_dev.  Limit: that array holds 512 partials
+ * of 1314 floats (2 690 048 bytes) per device, independent of n, and each
+ * device keeps its copy until the process ends; LBM_EINVAL if the partials
+ * of n samples would not fit it, for n < 1 or a NULL pointer.  Every call on
+ * a device shares that device's array and leaves its contents behind: calls
+ * that overlap on one device race.  Allocates no memory. */
+int lbm_mlp_loss_grad_noalloc(const float *params_dev, const float *x_dev, const float *t_dev, int64_t n,
+                              float *grad_dev, float *loss_dev, void *stream);
+
 /* One Adam step on the first 1313 entries of params_dev with FP32 moment
  * buffers m_dev, v_dev [1313]; step is 1-based. */
 int lbm_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int64_t step, double lr,

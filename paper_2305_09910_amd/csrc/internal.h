@@ -107,6 +107,11 @@ hipError_t launch_mlp_forward(const float *params, const float *x, int64_t n, fl
 size_t mlp_work_bytes(int64_t n);
 hipError_t launch_mlp_loss_grad(const float *params, const float *x, const float *t, int64_t n, float *grad,
                                 float *loss, void *work, hipStream_t s);
+// the same with the partial gradients in the library's static scratch array
+// instead of a caller workspace (hipErrorInvalidValue if they would not fit)
+size_t mlp_noalloc_scratch_bytes();
+hipError_t launch_mlp_loss_grad_noalloc(const float *params, const float *x, const float *t, int64_t n,
+                                        float *grad, float *loss, hipStream_t s);
 hipError_t launch_mlp_adam(float *p, const float *g, float *m, float *v, int64_t step, float lr, float b1, float b2,
                            float eps, hipStream_t s);
 

@@ -510,6 +510,21 @@ int lbm_mlp_loss_grad(const float *params_dev, const float *x_dev, const float *
     return e == hipSuccess ? LBM_OK : hip_fail(nullptr, e, "mlp_loss_grad");
 }
 
+int lbm_mlp_loss_grad_noalloc(const float *params_dev, const float *x_dev, const float *t_dev, int64_t n,
+                              float *grad_dev, float *loss_dev, void *stream)
+{
+    if (n < 1) return fail(nullptr, LBM_EINVAL, "mlp_loss_grad_noalloc: n must be >= 1");
+    if (!params_dev || !x_dev || !t_dev || !grad_dev || !loss_dev)
+        return fail(nullptr, LBM_EINVAL, "mlp_loss_grad_noalloc: NULL pointer");
+    if (mlp_work_bytes(n) > mlp_noalloc_scratch_bytes())
+        return fail(nullptr, LBM_EINVAL,
+                    "mlp_loss_grad_noalloc: the partials of %lld samples need %zu bytes, more than the %zu-byte "
+                    "static scratch",
+                    (long long)n, mlp_work_bytes(n), mlp_noalloc_scratch_bytes());
+    hipError_t e = launch_mlp_loss_grad_noalloc(params_dev, x_dev, t_dev, n, grad_dev, loss_dev, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(nullptr, e, "mlp_loss_grad_noalloc");
+}
+
 int lbm_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int64_t step, double lr,
                  double beta1, double beta2, double eps, void *stream)
 {

@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
 #include "mlp_wave.h"
@@ -364,6 +365,55 @@ hipError_t launch_mlp_loss_grad(const float *params, const float *x, const float
     if (e != hipSuccess) return e;
     k_mlp_grad_final<<<(GRAD_WORDS + 255) / 256, 256, 0, s>>>((const float *)work, GRAD_BLOCKS, n, grad, loss);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Loss and gradient for callers that cannot allocate device memory (code
+// under graph capture, serving loops): the per-block partial gradients go to
+// a file-scope device array instead of a caller workspace.  Each device the
+// library runs on holds its own copy until the process ends.  Every call on a
+// device shares that copy, so calls that overlap on one device race.  Every
+// call writes each partial in full (blocks without samples write zeros), so
+// nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH_FLOATS = (size_t)GRAD_BLOCKS * GRAD_WORDS;
+static __device__ __align__(256) float scratch[NOALLOC_SCRATCH_FLOATS];
+
+size_t mlp_noalloc_scratch_bytes() { return NOALLOC_SCRATCH_FLOATS * sizeof(float); }
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static void *scratch_ptr[SCRATCH_MAX_DEVICES];
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device with that device current.  In host code the array's name is
+// only a stand-in for the symbol, never a device address.
+static hipError_t scratch_address(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_mlp_loss_grad_noalloc(const float *params, const float *x, const float *t, int64_t n,
+                                        float *grad, float *loss, hipStream_t s)
+{
+    if (mlp_work_bytes(n) > mlp_noalloc_scratch_bytes()) return hipErrorInvalidValue;
+    void *w = nullptr;
+    const hipError_t e = scratch_address(&w);
+    if (e != hipSuccess) return e;
+    return launch_mlp_loss_grad(params, x, t, n, grad, loss, w, s);
 }
 
 // ---------------------------------------------------------------------------

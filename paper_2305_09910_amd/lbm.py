@@ -32,7 +32,8 @@ EXPORTED = [
     "lbm_init_equilibrium", "lbm_set_pdfs", "lbm_get_pdfs", "lbm_gather_pdfs", "lbm_step", "lbm_time",
     "lbm_moments", "lbm_totals", "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
     "lbm_set_closure_weights", "lbm_closure_fallbacks", "lbm_box_filter4", "lbm_closure_dataset",
-    "lbm_mlp_forward", "lbm_mlp_work_bytes", "lbm_mlp_loss_grad", "lbm_mlp_adam", "lbm_stream_copy",
+    "lbm_mlp_forward", "lbm_mlp_work_bytes", "lbm_mlp_loss_grad", "lbm_mlp_loss_grad_noalloc", "lbm_mlp_adam",
+    "lbm_stream_copy",
 ]
 
 
@@ -93,6 +94,7 @@ def lib():
             "lbm_mlp_forward": (ctypes.c_int, [P, P, I64, P, P]),
             "lbm_mlp_work_bytes": (SZ, [I64]),
             "lbm_mlp_loss_grad": (ctypes.c_int, [P, P, P, I64, P, P, P, P]),
+            "lbm_mlp_loss_grad_noalloc": (ctypes.c_int, [P, P, P, I64, P, P, P]),
             "lbm_mlp_adam": (ctypes.c_int, [P, P, P, P, I64, D, D, D, D, P]),
             "lbm_stream_copy": (ctypes.c_int, [P, P, SZ, P]),
         }
@@ -342,6 +344,16 @@ def mlp_loss_grad(params, x, t, work=None, stream=None):
     _check(lib().lbm_mlp_loss_grad(params.data_ptr(), x.contiguous().data_ptr(), t.contiguous().data_ptr(), n,
                                    grad.data_ptr(), loss.data_ptr(), work.data_ptr(), s))
     return loss, grad
+
+
+def mlp_loss_grad_noalloc(params, x, t, grad, loss, stream=None):
+    """lbm_mlp_loss_grad_noalloc: loss and gradient into the caller's grad
+    [1313] and loss [1] FP32 device tensors, with no workspace (the library's
+    static scratch holds the partials; calls that overlap on one device race)."""
+    n = x.shape[0]
+    s = stream if stream is not None else _stream_ptr(x.device)
+    _check(lib().lbm_mlp_loss_grad_noalloc(params.data_ptr(), x.contiguous().data_ptr(), t.contiguous().data_ptr(),
+                                           n, grad.data_ptr(), loss.data_ptr(), s))
 
 
 def mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
