@@ -124,10 +124,16 @@ def init_params(x, t, seed=0, margin=0.25):
     xn = x.double().cpu().numpy()
     mu = xn.mean(0)
     sg = xn.std(0)
-    sg = np.where(sg > 0, sg, np.maximum(np.abs(mu), 1.0))
+    # a feature whose spread is below a relative 1e-6 of its size is constant
+    # (tau): its std is only the roundoff of the mean, so give it unit scale
+    const = sg <= 1e-6 * np.abs(mu)
+    sg = np.where(const, np.maximum(np.abs(mu), 1.0), sg)
     lo, hi = xn.min(0), xn.max(0)
+    # widen by `margin` of the width and by a relative 1e-6, so that a
+    # constant feature keeps a range wider than its float32 rounding
     w = hi - lo
-    lo, hi = lo - margin * w - 1e-30, hi + margin * w + 1e-30
+    pad = margin * w + 1e-6 * np.maximum(np.abs(lo), np.abs(hi)) + 1e-30
+    lo, hi = lo - pad, hi + pad
     rng = np.random.default_rng(seed)
     tm = max(float(t.mean()), 1e-6)
     b3 = math.log(math.expm1(tm))

@@ -214,6 +214,141 @@ def test_fused_mlp_closure_steps_from_nonequilibrium(steps, streaming):
     assert err < 1e-5
 
 
+def _sharp_net():
+    p, norm = net(9, b3=-6.0)
+    norm[:6] = 0.0
+    norm[6:12] = [1e-4, 1e-4, 1e-4, 1e-3, 1e-3, 0.5]
+    return p, norm
+
+
+def _oracle_mlp(shape, p, norm, tau, F, rho, u, steps, sigma_scale=1.0):
+    """Oracle channel run with the closure network; sigma_scale != 1 scales
+    the standardisation (then rounded to float32, as the GPU stores it)."""
+    o = oracle.Sim(19, shape, bc=(0, 0, 1, 1, 0, 0), tau=tau, force=F, closure=oracle.CL_MLP, cs=0.1)
+    n2 = norm.astype(np.float32).copy()
+    if sigma_scale != 1.0:
+        n2[6:12] = (n2[6:12].astype(np.float64) * sigma_scale).astype(np.float32)
+    o.set_mlp(p.astype(np.float32), n2)
+    o.init_equilibrium(rho, u)
+    o.step(steps)
+    return o
+
+
+def _flow_sensitivity(shape, p, norm, tau, F, rho, u, steps):
+    """The oracle's own response, after `steps` steps, to shifting every
+    standardised network input by one bfloat16 ulp (sigma scaled by
+    1 + 2^-9): the size of the divergence that bf16 rounding flips of the
+    inputs (FP32 features on the GPU, FP64 in the oracle) can set off."""
+    a = _oracle_mlp(shape, p, norm, tau, F, rho, u, steps).get_pdfs()
+    b = _oracle_mlp(shape, p, norm, tau, F, rho, u, steps, 1.0 + 2.0 ** -9).get_pdfs()
+    return float(np.max(np.abs(a - b) / np.abs(a)))
+
+
+def _per_step_errors(g, o, steps):
+    """Step the GPU lattice `steps` times; before each step load its state
+    into the oracle and take one oracle step from it.  Returns, per step, the
+    largest relative population error and the fraction of populations whose
+    relative error exceeds 1e-5."""
+    errs, fracs = [], []
+    for _ in range(steps):
+        o.set_pdfs(g.get_pdfs().cpu().numpy())
+        o.step(1)
+        g.step(1)
+        a = g.get_pdfs().cpu().numpy()
+        b = o.get_pdfs()
+        e = np.abs(a - b) / np.abs(b)
+        errs.append(float(e.max()))
+        fracs.append(float(np.mean(e > 1e-5)))
+    return errs, fracs
+
+
+@pytest.mark.parametrize("streaming", ["aa", "et", "sparse"])
+def test_fused_mlp_sharp_network_every_step_of_60(streaming):
+    """A sharp random network at tau = 0.51 along a 60-step channel
+    trajectory: every GPU step against one oracle step from the GPU's own
+    state, so differences cannot build up over steps.  One step can still
+    differ where a standardised input sits on a bfloat16 rounding boundary:
+    the GPU forms the features in FP32, the oracle in FP64, and moving sigma
+    by one FP32 ulp moves the oracle's own single step by up to 5e-5 on this
+    trajectory.  Such flips touch single cells, so the bar is: at every step
+    at most 0.2% of the populations beyond 1e-5 and none beyond 1e-3 (an
+    output-bias error of 0.01 puts ~20% of them beyond 1e-5)."""
+    lbm = _lbm()
+    p, norm = _sharp_net()
+    shape, F = (32, 16, 8), (3e-6, 0, 0)
+    bc = ("periodic", "periodic", "noslip", "noslip", "periodic", "periodic")
+    g = lbm.Lattice(shape, q=19, tau=0.51, force=F, bc=bc, closure="mlp", cs=0.1, streaming=streaming)
+    g.set_closure_weights(np.r_[p, norm].astype(np.float32))
+    rho, u = inputs.channel(*shape, 0.08, 0.2, seed=11)
+    g.init_equilibrium(rho, u)
+    o = _oracle_mlp(shape, p, norm, 0.51, F, rho, u, 0)
+    errs, fracs = _per_step_errors(g, o, 60)
+    print(f"sharp network per step: worst {max(errs):.3e}, largest fraction beyond 1e-5 {max(fracs):.2e}, "
+          f"steps with any {sum(f > 0 for f in fracs)}")
+    assert max(fracs) <= 2e-3
+    assert max(errs) < 1e-3
+
+
+@pytest.mark.parametrize("streaming", ["aa", "et", "sparse"])
+def test_fused_mlp_sharp_network_60_steps_within_flow_sensitivity(streaming):
+    """The same sharp network over 60 steps end to end.  Here the flow itself
+    amplifies rounding: moving sigma by one FP32 ulp moves the oracle's own
+    populations by ~5e-4 after 60 steps, so no FP32 implementation can meet
+    1e-5.  The bar is three times the oracle's own response to a one-bf16-ulp
+    shift of every standardised input, measured here on the CPU; a planted
+    sign error of one feature moves the oracle by 6e-2."""
+    p, norm = _sharp_net()
+    shape, F = (32, 16, 8), (3e-6, 0, 0)
+    rho, u = inputs.channel(*shape, 0.08, 0.2, seed=11)
+    bound = 3.0 * _flow_sensitivity(shape, p, norm, 0.51, F, rho, u, 60)
+    g, o = _mlp_pair(shape, p, norm, 60, 19, tau=0.51, streaming=streaming)
+    a = g.get_pdfs().cpu().numpy()
+    b = o.get_pdfs()
+    err = float(np.max(np.abs(a - b) / np.abs(b)))
+    print(f"sharp network 60 steps: err {err:.3e}, bound {bound:.3e}")
+    assert 1e-5 < bound < 2e-2
+    assert err < bound
+
+
+def _trained_net():
+    import os
+    d = np.load(os.path.join(os.path.dirname(__file__), "golden", "closure_net_oracle_trained.npz"))
+    return (d["params"].astype(np.float64), d["norm"].astype(np.float64), float(d["tau_c"]),
+            (float(d["force_c"]), 0.0, 0.0), d["rho"], d["u"])
+
+
+@pytest.mark.parametrize("streaming", ["aa", "et", "sparse"])
+def test_fused_mlp_oracle_trained_network(streaming):
+    """A network trained by the oracle alone (tests/golden/make_closure_net.py:
+    filtered fine channel -> dataset -> Adam), run from its filtered coarse
+    start state (32x16x16, tau = 0.503) for 60 steps: end to end within three
+    times the flow's own response to a one-bf16-ulp input shift (or 1e-5);
+    fallback counts agree to 0.1% of the cell updates; then 20 more steps,
+    each against one oracle step from the GPU's state, under the bar of the
+    sharp network (one FP32 ulp of sigma moves the oracle's own step by up
+    to 6e-6 here, one bf16 ulp by up to 4e-5)."""
+    lbm = _lbm()
+    p, norm, tau, F, rho, u = _trained_net()
+    shape = rho.shape[::-1]
+    bc = ("periodic", "periodic", "noslip", "noslip", "periodic", "periodic")
+    g = lbm.Lattice(shape, q=19, tau=tau, force=F, bc=bc, closure="mlp", cs=0.1, streaming=streaming)
+    g.set_closure_weights(np.r_[p, norm].astype(np.float32))
+    g.init_equilibrium(rho, u)
+    g.step(60)
+    o = _oracle_mlp(shape, p, norm, tau, F, rho, u, 60)
+    a = g.get_pdfs().cpu().numpy()
+    b = o.get_pdfs()
+    err = float(np.max(np.abs(a - b) / np.abs(b)))
+    bound = max(1e-5, 3.0 * _flow_sensitivity(shape, p, norm, tau, F, rho, u, 60))
+    fb_g, fb_o = g.closure_fallbacks(), o.fallbacks
+    print(f"trained network 60 steps: err {err:.3e}, bound {bound:.3e}, fallbacks gpu {fb_g} oracle {fb_o}")
+    assert err < bound
+    assert abs(fb_g - fb_o) <= 1e-3 * 60 * g.n
+    errs, fracs = _per_step_errors(g, o, 20)
+    print(f"trained network per step: worst {max(errs):.3e}, largest fraction beyond 1e-5 {max(fracs):.2e}")
+    assert max(fracs) <= 2e-3 and max(errs) < 1e-4
+
+
 def test_fused_mlp_fallback_to_smagorinsky():
     """An empty trusted range sends every cell to the Smagorinsky fallback."""
     lbm = _lbm()
