@@ -42,11 +42,12 @@ INOUT_X = ("velocity", "pressure", "periodic", "periodic", "periodic", "periodic
 BYTES = {"f32": 4, "f16": 2, "bf16": 2}
 
 
-def bytes_per_cell(q, value_bytes, mask=False):
+def bytes_per_cell(q, value_bytes, mask=False, hrr=False):
     """Algorithmic HBM bytes of one cell update (the paper's n_b, Section 5.2):
     each of the q populations is read once and written once, plus the solid
-    flag of the cell when the domain has one."""
-    return 2 * q * value_bytes + (1 if mask else 0)
+    flag of the cell when the domain has one; the HRR collision also reads the
+    previous step's velocity (3 FP32) and writes its own."""
+    return 2 * q * value_bytes + (1 if mask else 0) + (24 if hrr else 0)
 
 
 def sparse_bytes_per_fluid_cell(q, value_bytes, table_every_step=False):
@@ -69,7 +70,7 @@ def log(*a):
 def channel_cfg(nx, ny, nz, storage="f32", closure="none", collision="trt"):
     F = 8 * (1 / 300) * 0.05 / ny ** 2  # centre-line u ~ 0.05 at tau = 0.51
     return dict(name=f"channel_{nx}x{ny}x{nz}", shape=(nx, ny, nz), q=19, tau=0.51, force=(F, 0, 0), bc=WALLS_Y,
-                storage=storage, closure=closure, solid=None, u_bc=None, collision=collision)
+                storage=storage, closure=closure, solid=None, u_bc=None, collision=collision, hrr_sigma=0.995)
 
 
 def obstacle_cfg(n=384, collision="trt"):
@@ -150,7 +151,7 @@ def make_lattice(cfg):
     lat = lbm.Lattice(cfg["shape"], q=cfg["q"], tau=cfg["tau"], force=cfg["force"], bc=cfg["bc"],
                       u_bc=cfg["u_bc"], solid=cfg["solid"], storage=cfg["storage"], closure=cfg["closure"],
                       collision=cfg.get("collision", "trt"), mrt_rates=cfg.get("mrt_rates"),
-                      streaming=cfg.get("streaming", "aa"))
+                      streaming=cfg.get("streaming", "aa"), hrr_sigma=cfg.get("hrr_sigma"))
     if cfg["closure"] == "mlp":
         lat.set_closure_weights(demo_closure_weights())
     rho, u = initial_fields(cfg)
@@ -202,7 +203,8 @@ def time_lattice(cfg, steps, warmup, diag_every=1000):
         res["bytes_per_fluid_cell"] = nb
         moved = nb * nfluid
     else:
-        nb = bytes_per_cell(cfg["q"], BYTES[cfg["storage"]], cfg["solid"] is not None)
+        nb = bytes_per_cell(cfg["q"], BYTES[cfg["storage"]], cfg["solid"] is not None,
+                            cfg.get("collision") == "hrr")
         moved = nb * n
     res["bytes_per_cell"] = nb if moved == nb * n else moved / n
     res["achieved_gbs"] = moved / (res["kernel_ms"] * 1e-3) / 1e9
@@ -246,6 +248,7 @@ L2_REFS = {
     "channel_64x32x32_smagorinsky": (lambda: channel_cfg(64, 32, 32, closure="smagorinsky"), 1000),
     "channel_64x32x32_mlp_closure": (lambda: channel_cfg(64, 32, 32, closure="mlp"), 200),
     "channel_64x32x32_mrt": (lambda: channel_cfg(64, 32, 32, collision="mrt"), 1000),
+    "channel_64x32x32_hrr": (lambda: channel_cfg(64, 32, 32, collision="hrr"), 1000),
     "obstacles_64^3_d3q27_mrt": (lambda: obstacle_cfg(64, collision="mrt"), 200),
     "porous_64^3_d3q19": (lambda: porous_cfg(64), 500),
 }
@@ -267,6 +270,8 @@ def l2_ref_of(form):
         return "channel_64x32x32_mlp_closure"
     if form.endswith("_mrt"):
         return "channel_64x32x32_mrt"
+    if form.endswith("_hrr"):
+        return "channel_64x32x32_hrr"
     return "channel_128x64x64"
 
 
@@ -282,6 +287,8 @@ def run_oracle(cfg, steps):
                    u_bc=cfg["u_bc"], solid=cfg["solid"], closure=cl, cs=0.1)
     if cfg.get("collision") == "mrt":
         o.set_mrt(cfg["mrt_rates"] if cfg["q"] == 27 else oracle.MRT_DHUMIERES)
+    if cfg.get("collision") == "hrr":
+        o.set_hrr(cfg["hrr_sigma"])
     if cl == oracle.CL_MLP:
         w = demo_closure_weights().astype(np.float64)
         o.set_mlp(w[:1313], w[1313:])
@@ -378,7 +385,8 @@ PAPER_CONTEXT = {
 
 FORMS = ["channel_256x128x128_f32", "channel_512x256x256_f32", "channel_512x256x256_f16",
          "channel_512x256x256_bf16", "channel_256x128x128_smagorinsky", "channel_256x128x128_mlp_closure",
-         "channel_512x256x256_mlp_closure", "channel_512x256x256_mrt", "obstacles_384^3_d3q27_mrt",
+         "channel_512x256x256_mlp_closure", "channel_512x256x256_mrt", "channel_512x256x256_hrr",
+         "obstacles_384^3_d3q27_mrt",
          "channel_256x128x128_et", "channel_512x256x256_f32_et", "channel_512x256x256_f16_et",
          "obstacles_384^3_d3q27_et", "porous_256^3_d3q19_f32", "porous_256^3_d3q19_f32_sparse",
          "porous_256^3_d3q19_f16", "porous_256^3_d3q19_f16_sparse", "channel_256x128x128_mlp_closure_et"]
@@ -404,6 +412,7 @@ def form_cfg(key, sized=True):
         "channel_256x128x128_mlp_closure": lambda: channel_cfg(256, 128, 128, "f32", "mlp"),
         "channel_512x256x256_mlp_closure": lambda: channel_cfg(512, 256, 256, "f32", "mlp"),
         "channel_512x256x256_mrt": lambda: channel_cfg(512, 256, 256, "f32", collision="mrt"),
+        "channel_512x256x256_hrr": lambda: channel_cfg(512, 256, 256, "f32", collision="hrr"),
         "obstacles_384^3_d3q27_mrt": lambda: obstacle_cfg(collision="mrt"),
         "channel_256x128x128_et": lambda: dict(channel_cfg(256, 128, 128, "f32"), streaming="et"),
         "channel_512x256x256_f32_et": lambda: dict(channel_cfg(512, 256, 256, "f32"), streaming="et"),

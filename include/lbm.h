@@ -52,7 +52,7 @@ extern "C" {
 /* Error codes. */
 #define LBM_OK 0
 #define LBM_EINVAL (-1)     /* invalid argument (sizes, enums, NULL, small workspace) */
-#define LBM_ENOMEM (-2)     /* the domain does not fit the 32-bit cell indexing or host memory */
+#define LBM_ENOMEM (-2)     /* the domain exceeds the indexing (sparse addressing: 2^32 cells, 2^31 fluid cells) or host memory */
 #define LBM_EDEVICE (-3)    /* a HIP runtime call or kernel launch failed */
 #define LBM_ENONFINITE (-4) /* lbm_totals found a NaN or Inf population */
 #define LBM_ESTATE (-5)     /* call not valid in the current state (e.g. MLP weights missing) */
@@ -88,8 +88,17 @@ enum { LBM_LES_NONE = 0, LBM_LES_SMAGORINSKY = 1, LBM_LES_MLP = 2 };
  *      1/tau, the ghost moments with mrt_rates = {energy, energy square,
  *      heat flux, fourth-order, third-order anti-symmetric}.  D3Q19 uses its
  *      19 orthogonal polynomial moments, D3Q27 the tensor products of
- *      {1, c, 3c^2 - 2}.  Not combinable with the learned closure. */
-enum { LBM_COLL_TRT = 0, LBM_COLL_MRT = 1 };
+ *      {1, c, 3c^2 - 2}.  Not combinable with the learned closure.
+ * HRR: hybrid recursive regularisation (the paper's "D3Q19HRR" of the LaBS
+ *      section, Section 4; after Jacob, Malaspinas & Sagaut 2018), D3Q19,
+ *      dense AA streaming, no closure: the non-equilibrium part is rebuilt
+ *      from its second-order Hermite coefficients, a blend hrr_sigma *
+ *      (projected flux) + (1 - hrr_sigma) * (-2 rho c_s^2 tau S) with S the
+ *      strain rate from finite differences of the previous step's velocity
+ *      field, and third-order coefficients by recursion; the equilibrium
+ *      carries the third-order terms the lattice supports.  The context keeps
+ *      two velocity fields (24 bytes per cell) in its state. */
+enum { LBM_COLL_TRT = 0, LBM_COLL_MRT = 1, LBM_COLL_HRR = 2 };
 
 /* In-place streaming schemes (one population set in HBM; Section 5.2).
  * AA: even steps read and write only the cell's own slots, odd steps read
@@ -112,7 +121,7 @@ enum { LBM_STREAM_AA = 0, LBM_STREAM_ET = 1, LBM_STREAM_AA_SPARSE = 2 };
 typedef struct lbm_ctx lbm_ctx;
 
 typedef struct lbm_domain {
-    int32_t nx, ny, nz;      /* cells, x fastest; each >= 1 */
+    int32_t nx, ny, nz;      /* cells, x fastest; each >= 1, ny and nz <= 65535 (cell indices are 64-bit) */
     int32_t bc[6];           /* LBM_BC_* per face -x,+x,-y,+y,-z,+z */
     double u_bc[6][3];       /* wall velocity of velocity faces */
     double rho_bc[6];        /* wall density of velocity and pressure faces (1.0 by default) */
@@ -124,6 +133,7 @@ typedef struct lbm_domain {
     int32_t collision;       /* LBM_COLL_* (TRT by default) */
     double mrt_rates[5];     /* MRT ghost rates in (0, 2); default 1.19, 1.4, 1.2, 1.4, 1.98 */
     int32_t streaming;       /* LBM_STREAM_* (AA by default) */
+    double hrr_sigma;        /* HRR weight of the projected flux in [0, 1] (0.995 by default) */
     void *workspace;         /* device memory of workspace_bytes bytes, 256-byte aligned */
     size_t workspace_bytes;
     void *stream;            /* hipStream_t; NULL = the default stream */
@@ -131,8 +141,8 @@ typedef struct lbm_domain {
 
 /* Fill *d with defaults: all faces periodic, rho_bc = 1, u_bc = 0, F32
  * storage, no closure, no flags, magic = 3/16, cs_smag = 0.1, TRT
- * collision, MRT ghost rates {1.19, 1.4, 1.2, 1.4, 1.98}, AA streaming, no
- * workspace.  The domain carries the free parameters of the kernel
+ * collision, MRT ghost rates {1.19, 1.4, 1.2, 1.4, 1.98}, AA streaming,
+ * hrr_sigma = 0.995, no workspace.  The domain carries the free parameters of the kernel
  * interface the paper describes for its generated kernels (raw pointers,
  * shape and free parameters; Section 3).  d == NULL: no effect. */
 void lbm_domain_defaults(lbm_domain *d);
@@ -232,8 +242,9 @@ int lbm_totals(lbm_ctx *ctx, double *mass, double mom[3]);
  * set kept in place, Section 5.2): q rows of sx cells per stored row,
  * sx = nx rounded up to whole 128-byte lines, with the Esoteric Twist's
  * ghost layers included; with sparse addressing q values per fluid cell, in
- * chunks of 64.  Its layout is internal; only lbm_load_state of a context
- * with the same domain and flags reads it back.  LBM_EINVAL for NULL. */
+ * chunks of 64; with the HRR collision followed by its two velocity
+ * fields.  Its layout is internal; only lbm_load_state of a context with
+ * the same domain and flags reads it back.  LBM_EINVAL for NULL. */
 int lbm_state_bytes(const lbm_ctx *ctx, size_t *out);
 
 /* Copy the raw state (the PDF set of Section 5.2's in-place streaming) to
@@ -268,7 +279,8 @@ int lbm_closure_fallbacks(lbm_ctx *ctx, int64_t *count);
 /* ------------------------------------------------------------------------ */
 
 /* Box filter over non-overlapping 4x4x4 blocks of fine FP32 fields
- * rho_dev [n], u_dev [3][n] (nx, ny, nz multiples of 4) into out_dev
+ * rho_dev [n], u_dev [3][n] (nx, ny, nz multiples of 4, fewer than 2^31
+ * cells, else LBM_ENOMEM) into out_dev
  * [10][n/64] FP32: rho, u_x, u_y, u_z, then the filtered products uu in
  * the order xx, yy, zz, xy, xz, yz. */
 int lbm_box_filter4(int32_t nx, int32_t ny, int32_t nz, const float *rho_dev, const float *u_dev, float *out_dev,
@@ -277,8 +289,9 @@ int lbm_box_filter4(int32_t nx, int32_t ny, int32_t nz, const float *rho_dev, co
 /* Closure dataset from filtered coarse fields filt_dev [10][n] (cx, cy, cz
  * cells, periodic[3] per axis; non-periodic axes have walls halfway outside
  * the first/last cell): features x_dev [n][6] and target dtau t_dev [n],
- * FP32.  tau is the molecular relaxation time of the coarse lattice, cs the
- * Smagorinsky constant used for feature 5. */
+ * FP32 (fewer than 2^31 coarse cells, else LBM_ENOMEM).  tau is the
+ * molecular relaxation time of the coarse lattice, cs the Smagorinsky
+ * constant used for feature 5. */
 int lbm_closure_dataset(int32_t cx, int32_t cy, int32_t cz, const int32_t periodic[3], const float *filt_dev,
                         double tau, double cs, float *x_dev, float *t_dev, void *stream);
 

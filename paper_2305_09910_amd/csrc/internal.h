@@ -9,7 +9,7 @@ namespace lbm {
 
 enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 enum { CL_NONE = 0, CL_SMAG = 1, CL_MLP = 2 };
-enum { COLL_TRT = 0, COLL_MRT = 1 };
+enum { COLL_TRT = 0, COLL_MRT = 1, COLL_HRR = 2 };
 enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
 
 // Bit 31 of a cell's mask word marks the cell itself as solid; bit i
@@ -37,7 +37,7 @@ struct LatticeArgs {
     void *pdf;               // [z][y][q][x] storage elements (deviations f_i - w_i)
     const uint32_t *mask;    // [n] or nullptr
     int nx, ny, nz;
-    uint32_t n;              // cells
+    uint32_t nrows;          // cell rows ny * nz (< 2^32; the cell count nrows * nx is 64-bit)
     int sx, sy;              // cells per stored row and rows per stored plane: nx, ny, or one more
                              // for the ghost layer of the Esoteric Twist on a non-periodic + face
     int et;                  // streaming scheme: 0 AA pattern, 1 Esoteric Twist
@@ -55,6 +55,9 @@ struct LatticeArgs {
     unsigned long long *fallbacks;  // MLP fallback counter (device) or nullptr
 };
 
+// cell count of a lattice
+__host__ __device__ inline uint64_t cells(const LatticeArgs &a) { return (uint64_t)a.nrows * (uint32_t)a.nx; }
+
 // Sparse addressing (the AA pattern over the fluid cells only), passed as an
 // argument of its own to the kernels that use it: the dense step kernels keep
 // exactly their argument block (its layout moves their compiled code).
@@ -65,6 +68,16 @@ struct SparseArgs {
     const uint32_t *nbt;     // neighbour table [chunk][q - 1][64]
 };
 
+// Hybrid recursive regularised collision (D3Q19): the velocity fields of its
+// finite-difference gradient, passed as a kernel argument of its own (after
+// the others, so that the dense kernels' argument block keeps its layout).
+// Step t reads the field of step t - 1 and writes its own.
+struct HrrArgs {
+    const float *uprev;  // [3][n] velocities of the previous step
+    float *unext;        // [3][n] velocities of this step
+    float sigma;         // weight of the projected non-equilibrium flux
+};
+
 struct Launch {
     dim3 grid, block;
 };
@@ -72,7 +85,7 @@ Launch lattice_launch(const LatticeArgs &a);
 
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, uint32_t *mask, hipStream_t s);
-hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
+hipError_t launch_step(const LatticeArgs &a, const HrrArgs &h, int q, int st, int cl, int coll, int odd, hipStream_t s);
 // Esoteric Twist step (lbm_et.hip)
 hipError_t launch_step_et(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);
 // sparse addressing (lbm_sparse.hip): neighbour table from the fluid map and

@@ -138,7 +138,7 @@ struct Store<ST_BF16> {
 // ---------------------------------------------------------------------------
 struct Geom {
     int x, y, z;
-    uint32_t c;    // cell index (z ny + y) nx + x of fields and the mask
+    uint32_t frow; // row z ny + y of the cell fields and the mask (cell index frow nx + x: cidx)
     uint32_t row;  // row index z sy + y of the population store
     int xm, xp, ym, yp, zm, zp;    // wrapped neighbour coordinates
     int xq, yq, zq;                // x + 1 etc. in the store: wrapped on periodic axes, else the ghost layer
@@ -152,7 +152,7 @@ __device__ inline Geom make_geom(const LatticeArgs &a, int x, int y, int z)
     g.y = y;
     g.z = z;
     g.row = (uint32_t)z * (uint32_t)a.sy + (uint32_t)y;
-    g.c = ((uint32_t)z * (uint32_t)a.ny + (uint32_t)y) * (uint32_t)a.nx + (uint32_t)x;
+    g.frow = (uint32_t)z * (uint32_t)a.ny + (uint32_t)y;
     g.xm = x == 0 ? a.nx - 1 : x - 1;
     g.xp = x == a.nx - 1 ? 0 : x + 1;
     g.ym = y == 0 ? a.ny - 1 : y - 1;
@@ -171,13 +171,20 @@ __device__ inline Geom make_geom(const LatticeArgs &a, int x, int y, int z)
     return g;
 }
 
+// 64-bit cell index (z ny + y) nx + x of the fields and the mask, formed
+// only where a kernel uses it
+__device__ inline uint64_t cidx(const LatticeArgs &a, const Geom &g)
+{
+    return (uint64_t)g.frow * (uint32_t)a.nx + (uint32_t)g.x;
+}
+
 // index of the neighbour at offset (dx, dy, dz), periodic wrap
-__device__ inline uint32_t nbr(const LatticeArgs &a, const Geom &g, int dx, int dy, int dz)
+__device__ inline uint64_t nbr(const LatticeArgs &a, const Geom &g, int dx, int dy, int dz)
 {
     const int xx = dx < 0 ? g.xm : (dx > 0 ? g.xp : g.x);
     const int yy = dy < 0 ? g.ym : (dy > 0 ? g.yp : g.y);
     const int zz = dz < 0 ? g.zm : (dz > 0 ? g.zp : g.z);
-    return ((uint32_t)zz * (uint32_t)a.ny + (uint32_t)yy) * (uint32_t)a.nx + (uint32_t)xx;
+    return (uint64_t)((uint32_t)zz * (uint32_t)a.ny + (uint32_t)yy) * (uint32_t)a.nx + (uint32_t)xx;
 }
 
 // Population store: rows of q direction segments, [z][y][i][x].  Each
@@ -550,6 +557,126 @@ __device__ inline void mrt_collide(const LatticeArgs &a, float (&d)[Q], float dr
     });
 }
 
+// ---------------------------------------------------------------------------
+// hybrid recursive regularised collision (HRR, D3Q19; the "D3Q19HRR" of the
+// LaBS section, after Jacob, Malaspinas & Sagaut 2018)
+// ---------------------------------------------------------------------------
+// Velocity gradient G[a][b] = d u_a / d x_b of the previous step's velocity
+// field U [3][n] at a fluid cell.  Per axis: central differences between two
+// domain neighbours (periodic faces wrap); next to a wall half a cell away
+// (a no-slip face, a velocity face with its u_bc, or a solid neighbour at
+// rest) the derivative of the quadratic through the wall point and the two
+// nearest cells, -4/3 u_w + u_0 + u_1/3 (mirrored on the + side); between two
+// walls u_w+ - u_w-; a pressure face's ghost takes the cell's own velocity.
+template <int Q>
+__device__ inline void fd_gradient(const LatticeArgs &a, const HrrArgs &h, const Geom &g, uint32_t m,
+                                   float (&G)[3][3])
+{
+    const float *U = h.uprev;
+    const uint64_t n = cells(a);
+    float u0[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u0[k] = U[k * n + cidx(a, g)];
+    for_dirs<0, 3>([&](auto B) {
+        constexpr int b = decltype(B)::value;
+        constexpr int dm = 2 * b + 2, dp = 2 * b + 1;  // directions -e_b and +e_b
+        const bool cutm = b == 0 ? g.cxl : (b == 1 ? g.cyl : g.czl);
+        const bool cutp = b == 0 ? g.cxh : (b == 1 ? g.cyh : g.czh);
+        const int km = cutm ? (a.bc[2 * b] == BC_PRESSURE ? 2 : 1) : (int)((m >> dm) & 1u);
+        const int kp = cutp ? (a.bc[2 * b + 1] == BC_PRESSURE ? 2 : 1) : (int)((m >> dp) & 1u);
+        const bool velm = cutm && a.bc[2 * b] == BC_VELOCITY, velp = cutp && a.bc[2 * b + 1] == BC_VELOCITY;
+        const uint64_t im = km == 0 ? nbr(a, g, -cdir(dp, 0), -cdir(dp, 1), -cdir(dp, 2)) : cidx(a, g);
+        const uint64_t ip = kp == 0 ? nbr(a, g, cdir(dp, 0), cdir(dp, 1), cdir(dp, 2)) : cidx(a, g);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float um = U[k * n + im], up = U[k * n + ip];
+            const float wm = velm ? a.ubc[2 * b][k] : 0.f, wp = velp ? a.ubc[2 * b + 1][k] : 0.f;
+            float dd = 0.5f * (up - um);
+            if (km == 1) dd = -(4.f / 3.f) * wm + u0[k] + up * (1.f / 3.f);
+            if (kp == 1) dd = (4.f / 3.f) * wp - u0[k] - um * (1.f / 3.f);
+            if (km == 1 && kp == 1) dd = wp - wm;
+            G[k][b] = dd;
+        }
+    });
+}
+
+// HRR on deviations d_i = f_i - w_i, D3Q19:
+//   f*_i = feq_i + (1 - 1/tau) f1_i + S_i / 2,
+//   f1_i = w_i [ 9/2 H2_i : Pi + sum_k T_k(c_i) A_k / N_k ],
+// Pi = sigma P_c + (1 - sigma)(-1/3 rho tau (G + G^T)) blends the projected
+// non-equilibrium flux with the finite-difference one; A_k combine the
+// recursive third-order coefficients a3_abg = u_a Pi_bg + u_b Pi_ag +
+// u_g Pi_ab; the equilibrium adds the same third-order terms with
+// a3 = rho u u u.  (BGK with Guo forcing is feq + (1 - 1/tau)(f - feq + S/2)
+// + S/2; the regularisation replaces the middle term by f1.)  keep: leave
+// the populations as they are (solid lanes on the even step).
+template <int Q>
+__device__ inline void hrr_collide(const LatticeArgs &a, float sigma, const float (&G)[3][3], float (&d)[Q],
+                                   float drho, const Macro &M, bool keep)
+{
+    static_assert(Q == 19, "HRR is built for D3Q19");
+    if (keep) return;
+    float P[6];
+    noneq_flux<Q>(a, d, drho, M, P);
+    const float fd = -(1.f / 3.f) * M.rho * a.tau, s1 = 1.f - sigma;
+    const float pxx = sigma * P[0] + s1 * fd * 2.f * G[0][0];
+    const float pyy = sigma * P[1] + s1 * fd * 2.f * G[1][1];
+    const float pzz = sigma * P[2] + s1 * fd * 2.f * G[2][2];
+    const float pxy = sigma * P[3] + s1 * fd * (G[0][1] + G[1][0]);
+    const float pxz = sigma * P[4] + s1 * fd * (G[0][2] + G[2][0]);
+    const float pyz = sigma * P[5] + s1 * fd * (G[1][2] + G[2][1]);
+    const float ux = M.ux, uy = M.uy, uz = M.uz;
+    // recursive third-order coefficients, combined as the lattice carries them
+    const float xxy = 2.f * ux * pxy + uy * pxx, yzz = 2.f * uz * pyz + uy * pzz;
+    const float xzz = 2.f * uz * pxz + ux * pzz, xyy = 2.f * uy * pxy + ux * pyy;
+    const float yyz = 2.f * uy * pyz + uz * pyy, xxz = 2.f * ux * pxz + uz * pxx;
+    const float R = M.rho;
+    const float e_xxy = R * ux * ux * uy, e_yzz = R * uy * uz * uz, e_xzz = R * ux * uz * uz;
+    const float e_xyy = R * ux * uy * uy, e_yyz = R * uy * uy * uz, e_xxz = R * ux * ux * uz;
+    const float k1 = 1.f - a.omp;
+    // per combination: (1 - 1/tau) A_k / N_k + A^eq_k / N_k
+    // (the norms are compile-time constants: 27/2 for the sums, 27/6 for the differences)
+    constexpr float iN0 = (float)(1.0 / t3norm(0)), iN1 = (float)(1.0 / t3norm(1)), iN2 = (float)(1.0 / t3norm(2));
+    constexpr float iN3 = (float)(1.0 / t3norm(3)), iN4 = (float)(1.0 / t3norm(4)), iN5 = (float)(1.0 / t3norm(5));
+    float Bk[6];
+    Bk[0] = (k1 * (xxy + yzz) + (e_xxy + e_yzz)) * iN0;
+    Bk[1] = (k1 * (xxy - yzz) + (e_xxy - e_yzz)) * iN1;
+    Bk[2] = (k1 * (xzz + xyy) + (e_xzz + e_xyy)) * iN2;
+    Bk[3] = (k1 * (xzz - xyy) + (e_xzz - e_xyy)) * iN3;
+    Bk[4] = (k1 * (yyz + xxz) + (e_yyz + e_xxz)) * iN4;
+    Bk[5] = (k1 * (yyz - xxz) + (e_yyz - e_xxz)) * iN5;
+    const float F0 = a.F[0], F1 = a.F[1], F2 = a.F[2];
+    const float usq = ux * ux + uy * uy + uz * uz;
+    const float uF = ux * F0 + uy * F1 + uz * F2;
+    const float base = drho - 1.5f * R * usq;
+    const float trp = (pxx + pyy + pzz) * (1.f / 3.f);
+    for_dirs<0, Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cx = cdir(i, 0), cy = cdir(i, 1), cz = cdir(i, 2);
+        constexpr float w = (float)wgt<Q>(i);
+        const float cu = cx * ux + cy * uy + cz * uz;
+        const float cF = cx * F0 + cy * F1 + cz * F2;
+        const float deq = w * (base + R * (3.f * cu + 4.5f * cu * cu));
+        const float h2 = (float)(cx * cx) * pxx + (float)(cy * cy) * pyy + (float)(cz * cz) * pzz +
+                         2.f * ((float)(cx * cy) * pxy + (float)(cx * cz) * pxz + (float)(cy * cz) * pyz) - trp;
+        float t3 = 0.f;
+        for_dirs<0, 6>([&](auto K) {
+            constexpr int k = decltype(K)::value;
+            constexpr float tv = (float)t3val(i, k);
+            if constexpr (tv != 0.f) t3 += tv * Bk[k];
+        });
+        const float S = w * (3.f * (cF - uF) + 9.f * cu * cF);
+        d[i] = deq + w * (k1 * 4.5f * h2 + t3) + 0.5f * S;
+    });
+    // The update keeps the cell's mass exactly (sum f* = rho); the rest
+    // population takes what the moving ones leave, so FP32 rounding of the
+    // moving ones cannot drift the total mass.
+    float moving = 0.f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) moving += d[i];
+    d[0] = drho - moving;
+}
+
 // Canonical read for the state kernels, any scheme.  With sparse addressing
 // (fluid cells only, the AA pattern over the fluid index) f_i sits after an
 // odd number of steps in slot opposite(i) of the neighbour x - c_i, or in the
@@ -565,7 +692,7 @@ __device__ inline void load_state(const LatticeArgs &a, const SparseArgs &sp, co
     }
     using S = Store<ST>;
     const typename S::T *A = (const typename S::T *)a.pdf;
-    const int32_t kf = sp.fmap[g.c];
+    const int32_t kf = sp.fmap[cidx(a, g)];
     if (kf < 0) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) d[i] = 0.f;
@@ -585,7 +712,7 @@ __device__ inline void load_state(const LatticeArgs &a, const SparseArgs &sp, co
 template <int Q>
 __device__ inline uint64_t index_t0(const LatticeArgs &a, const SparseArgs &sp, const Geom &g, int i)
 {
-    if (sp.on) return sp_index<Q>((uint32_t)sp.fmap[g.c], i);
+    if (sp.on) return sp_index<Q>((uint32_t)sp.fmap[cidx(a, g)], i);
     if (a.et) return et_index<Q>(a, g, i, cdir(i, 0) < 0, cdir(i, 1) < 0, cdir(i, 2) < 0);
     return pidx<Q>(a, i, g.row, g.x);
 }

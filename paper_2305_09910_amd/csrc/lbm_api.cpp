@@ -8,6 +8,9 @@
 //                with the Esoteric Twist each non-periodic axis has one more
 //                cell (the ghost layer beyond its + face); with sparse
 //                addressing q * nf elements in chunks of 64 fluid cells
+//   velocities   (HRR only) two velocity fields of 3 * n FP32, the input and
+//                output of the finite-difference gradient; with the
+//                populations they form the state that checkpoints copy
 //   mask         n uint32 words (only with use_flags)
 //   sparse       (sparse addressing only) fluid map (n int32), fluid cells'
 //                linear indices (nf uint32) and neighbour table ((q-1) * nf uint32)
@@ -30,6 +33,8 @@ using namespace lbm;
 struct lbm_ctx {
     LatticeArgs a;
     SparseArgs sp;
+    float *uvel[2];  // HRR velocity fields: step t reads uvel[t & 1], writes uvel[(t + 1) & 1]
+    float hrr_sigma;
     int q, st, cl, coll;
     int64_t time;
     hipStream_t stream;
@@ -72,7 +77,8 @@ static int hip_fail(lbm_ctx *c, hipError_t e, const char *what)
 static size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t pdf, mask, fmap, fcell, nbt, partial, final_out, mlp, mlp_tab, fallback, total, pdf_bytes;
+    size_t pdf, uvel, mask, fmap, fcell, nbt, partial, final_out, mlp, mlp_tab, fallback, total, pdf_bytes;
+    size_t uvel_bytes, state_bytes;  // one velocity field; populations plus velocity fields
     int sx, sy, sz;  // cells of the population store per axis
 };
 
@@ -91,7 +97,13 @@ static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c, int64_
     if (d->streaming != LBM_STREAM_AA && d->streaming != LBM_STREAM_ET && d->streaming != LBM_STREAM_AA_SPARSE)
         return fail(c, LBM_EINVAL, "unknown streaming scheme %d", d->streaming);
     const uint64_t n = (uint64_t)d->nx * (uint64_t)d->ny * (uint64_t)d->nz;
-    if (n >= (1ull << 31)) return fail(c, LBM_ENOMEM, "domain of %llu cells exceeds 2^31 cells", (unsigned long long)n);
+    // Cell indices are 64-bit; rows (z, y) are counted in 32 bits, and the
+    // launch grid spans ny and nz in its second and third dimension.
+    if (d->ny > 65535 || d->nz > 65535)
+        return fail(c, LBM_EINVAL, "ny and nz must be at most 65535 (got %d, %d)", d->ny, d->nz);
+    const bool sp = d->streaming == LBM_STREAM_AA_SPARSE;
+    if (sp && n >= (1ull << 32))
+        return fail(c, LBM_ENOMEM, "sparse addressing: domain of %llu cells exceeds 2^32 cells", (unsigned long long)n);
     const bool et = d->streaming == LBM_STREAM_ET;
     const size_t elem = d->storage == LBM_STORE_F32 ? 4 : 2;
     // Row pitch: whole 128-byte lines, so that every direction segment
@@ -103,15 +115,18 @@ static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c, int64_
     L->sy = d->ny + (et && d->bc[2] != LBM_BC_PERIODIC);
     L->sz = d->nz + (et && d->bc[4] != LBM_BC_PERIODIC);
     const uint64_t ns = (uint64_t)L->sx * (uint64_t)L->sy * (uint64_t)L->sz;
-    if (ns >= (1ull << 31))
-        return fail(c, LBM_ENOMEM, "store of %llu cells exceeds 2^31 cells", (unsigned long long)ns);
-    const bool sp = d->streaming == LBM_STREAM_AA_SPARSE;
     if (nf < 0 || nf > (int64_t)n) nf = (int64_t)n;
+    if (sp && nf >= (1ll << 31))
+        return fail(c, LBM_ENOMEM, "sparse addressing: %lld fluid cells exceed 2^31", (long long)nf);
     const uint64_t chunks = ((uint64_t)nf + SP_CHUNK - 1) / SP_CHUNK;
     size_t off = 0;
     L->pdf = off;
     L->pdf_bytes = sp ? (size_t)q * chunks * SP_CHUNK * elem : (size_t)q * ns * elem;
     off += al256(L->pdf_bytes);
+    L->uvel = off;
+    L->uvel_bytes = d->collision == LBM_COLL_HRR ? al256((size_t)12 * n) : 0;
+    off += 2 * L->uvel_bytes;
+    L->state_bytes = d->collision == LBM_COLL_HRR ? off : L->pdf_bytes;
     L->mask = off;
     if (d->use_flags) off += al256(4 * n);
     L->fmap = L->fcell = L->nbt = off;
@@ -153,6 +168,7 @@ void lbm_domain_defaults(lbm_domain *d)
     d->collision = LBM_COLL_TRT;
     const double r[5] = {1.19, 1.4, 1.2, 1.4, 1.98};
     for (int k = 0; k < 5; ++k) d->mrt_rates[k] = r[k];
+    d->hrr_sigma = 0.995;
 }
 
 int lbm_workspace_bytes(const lbm_domain *d, int stencil, size_t *out)
@@ -206,8 +222,16 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     for (int a = 0; a < 3; ++a)
         if ((d->bc[2 * a] == LBM_BC_PERIODIC) != (d->bc[2 * a + 1] == LBM_BC_PERIODIC))
             return fail(nullptr, LBM_EINVAL, "axis %d: a periodic face needs a periodic opposite face", a);
-    if (d->collision != LBM_COLL_TRT && d->collision != LBM_COLL_MRT)
+    if (d->collision != LBM_COLL_TRT && d->collision != LBM_COLL_MRT && d->collision != LBM_COLL_HRR)
         return fail(nullptr, LBM_EINVAL, "unknown collision %d", d->collision);
+    if (d->collision == LBM_COLL_HRR) {
+        if (stencil != LBM_D3Q19) return fail(nullptr, LBM_EINVAL, "the HRR collision is built for D3Q19");
+        if (d->streaming != LBM_STREAM_AA)
+            return fail(nullptr, LBM_EINVAL, "the HRR collision runs with the dense AA pattern only");
+        if (d->closure != LBM_LES_NONE) return fail(nullptr, LBM_EINVAL, "the HRR collision runs without a closure");
+        if (!(d->hrr_sigma >= 0.0 && d->hrr_sigma <= 1.0))
+            return fail(nullptr, LBM_EINVAL, "hrr_sigma must lie in [0, 1]");
+    }
     if (d->collision == LBM_COLL_MRT) {
         if (d->closure == LBM_LES_MLP) return fail(nullptr, LBM_EINVAL, "the MLP closure runs with TRT only");
         for (int k = 0; k < 5; ++k)
@@ -237,7 +261,10 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     c->mlp = (float *)(c->ws + L.mlp);
     c->fallbacks = (unsigned long long *)(c->ws + L.fallback);
     c->mask = d->use_flags ? (uint32_t *)(c->ws + L.mask) : nullptr;
-    c->state_bytes = L.pdf_bytes;
+    c->state_bytes = L.state_bytes;
+    c->uvel[0] = L.uvel_bytes ? (float *)(c->ws + L.uvel) : nullptr;
+    c->uvel[1] = L.uvel_bytes ? (float *)(c->ws + L.uvel + L.uvel_bytes) : nullptr;
+    c->hrr_sigma = (float)d->hrr_sigma;
 
     LatticeArgs &a = c->a;
     memset(&a, 0, sizeof a);
@@ -246,7 +273,8 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     a.nx = d->nx;
     a.ny = d->ny;
     a.nz = d->nz;
-    a.n = (uint32_t)((uint64_t)d->nx * d->ny * d->nz);
+    const uint64_t ncell = (uint64_t)d->nx * d->ny * d->nz;
+    a.nrows = (uint32_t)d->ny * (uint32_t)d->nz;
     a.sx = L.sx;
     a.sy = L.sy;
     a.et = d->streaming == LBM_STREAM_ET;
@@ -281,15 +309,15 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
         // least n bytes: the population store, or the fluid map (sparse)
         uint8_t *stage = (uint8_t *)(sp ? c->ws + L.fmap : a.pdf);
         if (flags)
-            e = hipMemcpyAsync(stage, flags, a.n, hipMemcpyHostToDevice, c->stream);
+            e = hipMemcpyAsync(stage, flags, ncell, hipMemcpyHostToDevice, c->stream);
         else
-            e = hipMemsetAsync(stage, 0, a.n, c->stream);
+            e = hipMemsetAsync(stage, 0, ncell, c->stream);
         if (e == hipSuccess) e = launch_build_mask(a, stencil, stage, c->mask, c->stream);
     }
     if (e == hipSuccess && sp) {
         // fluid index of every cell (row order) and the linear index of every
         // fluid cell; the neighbour table is built from them on the device
-        int32_t *fmap = new (std::nothrow) int32_t[a.n];
+        int32_t *fmap = new (std::nothrow) int32_t[ncell];  // ncell < 2^32 with sparse addressing
         uint32_t *fcell = new (std::nothrow) uint32_t[nf > 0 ? nf : 1];
         if (!fmap || !fcell) {
             delete[] fmap;
@@ -298,7 +326,7 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
             return fail(nullptr, LBM_ENOMEM, "out of host memory for the fluid map");
         }
         uint32_t k = 0;
-        for (uint32_t cell = 0; cell < a.n; ++cell) {
+        for (uint32_t cell = 0; cell < (uint32_t)ncell; ++cell) {
             if (flags && flags[cell]) {
                 fmap[cell] = -1;
             } else {
@@ -306,7 +334,7 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
                 fcell[k++] = cell;
             }
         }
-        e = hipMemcpyAsync(c->ws + L.fmap, fmap, (size_t)4 * a.n, hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpyAsync(c->ws + L.fmap, fmap, (size_t)4 * ncell, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess && nf > 0)
             e = hipMemcpyAsync(c->ws + L.fcell, fcell, (size_t)4 * nf, hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess)
@@ -334,13 +362,25 @@ int lbm_destroy(lbm_ctx *ctx)
 
 const char *lbm_last_error(const lbm_ctx *ctx) { return ctx ? ctx->err : g_err; }
 
+// HRR: the velocity field of the initial state (the finite-difference
+// gradient's input on the first step) into uvel[0] and uvel[1]; the moments
+// kernel's density output goes to uvel[1] first (it holds 3 n floats).
+static int hrr_fill_velocity(lbm_ctx *c)
+{
+    if (c->coll != LBM_COLL_HRR) return LBM_OK;
+    HIPCHECK(c, launch_moments(c->a, c->sp, c->q, c->st, 0, c->uvel[1], c->uvel[0], c->stream), "hrr velocity");
+    HIPCHECK(c, hipMemcpyAsync(c->uvel[1], c->uvel[0], (size_t)12 * cells(c->a), hipMemcpyDeviceToDevice, c->stream),
+             "hrr velocity copy");
+    return LBM_OK;
+}
+
 int lbm_init_equilibrium(lbm_ctx *c, const double *rho_dev, const double *u_dev)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
     if (!rho_dev || !u_dev) return fail(c, LBM_EINVAL, "rho/u is NULL");
     HIPCHECK(c, launch_init_eq(c->a, c->sp, c->q, c->st, rho_dev, u_dev, c->stream), "init_equilibrium");
     c->time = 0;
-    return LBM_OK;
+    return hrr_fill_velocity(c);
 }
 
 int lbm_set_pdfs(lbm_ctx *c, const double *f_dev)
@@ -349,7 +389,7 @@ int lbm_set_pdfs(lbm_ctx *c, const double *f_dev)
     if (!f_dev) return fail(c, LBM_EINVAL, "f is NULL");
     HIPCHECK(c, launch_set_pdfs(c->a, c->sp, c->q, c->st, f_dev, c->stream), "set_pdfs");
     c->time = 0;
-    return LBM_OK;
+    return hrr_fill_velocity(c);
 }
 
 int lbm_get_pdfs(lbm_ctx *c, double *f_dev)
@@ -369,6 +409,15 @@ int lbm_gather_pdfs(lbm_ctx *c, const int64_t *cells_dev, int64_t n, double *out
     return LBM_OK;
 }
 
+static HrrArgs hrr_args(const lbm_ctx *c, int odd)
+{
+    HrrArgs h;
+    h.uprev = c->uvel[odd];
+    h.unext = c->uvel[odd ^ 1];
+    h.sigma = c->hrr_sigma;
+    return h;
+}
+
 int lbm_step(lbm_ctx *c, int64_t n)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
@@ -379,7 +428,7 @@ int lbm_step(lbm_ctx *c, int64_t n)
         const int odd = (int)(c->time & 1);
         hipError_t e = c->sp.on  ? launch_step_sparse(c->a, c->sp, c->q, c->st, c->cl, c->coll, odd, c->stream)
                        : c->a.et ? launch_step_et(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream)
-                                 : launch_step(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream);
+                                 : launch_step(c->a, hrr_args(c, odd), c->q, c->st, c->cl, c->coll, odd, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "stream_collide launch");
         ++c->time;
     }

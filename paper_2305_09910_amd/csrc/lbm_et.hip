@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collid
     const Geom g = make_geom(a, active ? x : 0, active ? y : 0, z);
     uint32_t m = 0;
     if constexpr (MASK) {
-        m = active ? a.mask[g.c] : 0u;
+        m = active ? a.mask[cidx(a, g)] : 0u;
         if (m & SELF_SOLID) {
             if constexpr (CL != CL_MLP) return;
             active = false;
@@ -129,6 +129,7 @@ static void et_coll(const LatticeArgs &a, int cl, bool mk, int odd, const Launch
 hipError_t launch_step_et(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s)
 {
     if (cl == CL_MLP && coll == COLL_MRT) return hipErrorInvalidValue;
+    if (coll == COLL_HRR) return hipErrorInvalidValue;  // HRR runs with the dense AA pattern only
     const Launch L = lattice_launch(a);
     const bool mk = a.mask != nullptr;
     return dispatch(q, st, [&](auto Qc, auto STc) {

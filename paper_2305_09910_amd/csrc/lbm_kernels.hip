@@ -37,7 +37,8 @@ namespace lbm {
 // the fused stream-collide kernel
 // ---------------------------------------------------------------------------
 template <int Q, int ST, int CL, bool MASK, int COLL>
-__global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collide(LatticeArgs a, int odd)
+__global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES)
+    k_stream_collide(LatticeArgs a, int odd, [[maybe_unused]] HrrArgs h)
 {
     using S = Store<ST>;
     constexpr bool kUnified =
@@ -73,7 +74,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collid
     const Geom g = make_geom(a, active ? x : 0, active ? y : 0, z);
     uint32_t m = 0;
     if constexpr (MASK) {
-        m = active ? a.mask[g.c] : 0u;
+        m = active ? a.mask[cidx(a, g)] : 0u;
         if (m & SELF_SOLID) {
             if constexpr (kKeepSolid) {
                 if (odd) return;
@@ -103,17 +104,29 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES) k_stream_collid
     const Macro M = moments<Q>(a, d, drho);
     float wp, wm;
     closure_rates<Q, CL>(a, tab, d, drho, M, active, wp, wm);
-    if constexpr (COLL == COLL_MRT)
+    if constexpr (COLL == COLL_MRT) {
         mrt_collide<Q>(a, d, drho, M, wp, keep);
-    else
+    } else if constexpr (COLL == COLL_HRR) {
+        // finite-difference gradient of the previous step's velocities; this
+        // step's velocities go to the other field (solid cells keep zeros)
+        float G[3][3] = {};
+        if (!keep) {
+            fd_gradient<Q>(a, h, g, m, G);
+            h.unext[cidx(a, g)] = M.ux;
+            h.unext[cells(a) + cidx(a, g)] = M.uy;
+            h.unext[2 * cells(a) + cidx(a, g)] = M.uz;
+        }
+        hrr_collide<Q>(a, h.sigma, G, d, drho, M, keep);
+    } else {
         trt_collide<Q>(a, d, drho, M, wp, wm, keep);
+    }
     if constexpr (CL == CL_MLP) {
         if (!active) return;
     }
 
     typename S::T *A = (typename S::T *)a.pdf;
     if (kUnified) {
-        store_all<Q, ST, MASK, COLL == COLL_MRT>(a, g, m, odd, d, M, keep);
+        store_all<Q, ST, MASK, COLL != COLL_TRT>(a, g, m, odd, d, M, keep);
     } else if (plain) {
         store_plain<Q, ST, MASK>(a, g, m, odd, d);
     } else if (!odd) {
@@ -212,13 +225,13 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_build_mask(LatticeArgs a, co
     const int z = blockIdx.z;
     if (x >= a.nx || y >= a.ny) return;
     const Geom g = make_geom(a, x, y, z);
-    uint32_t m = flags[g.c] ? SELF_SOLID : 0u;
+    uint32_t m = flags[cidx(a, g)] ? SELF_SOLID : 0u;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const int dx = cdir(i, 0), dy = cdir(i, 1), dz = cdir(i, 2);
         if (!face_cut(g, dx, dy, dz) && flags[nbr(a, g, dx, dy, dz)]) m |= 1u << i;
     }
-    mask[g.c] = m;
+    mask[cidx(a, g)] = m;
 }
 
 template <int Q, int ST>
@@ -230,9 +243,9 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_init_eq(LatticeArgs a, Spars
     const int z = blockIdx.z;
     if (x >= a.nx || y >= a.ny) return;
     const Geom g = make_geom(a, x, y, z);
-    const bool solid = a.mask && (a.mask[g.c] & SELF_SOLID);
-    if (sp.on && sp.fmap[g.c] < 0) return;  // sparse addressing stores fluid cells only
-    const double r = rho[g.c], ux = u[g.c], uy = u[(uint64_t)a.n + g.c], uz = u[2 * (uint64_t)a.n + g.c];
+    const bool solid = a.mask && (a.mask[cidx(a, g)] & SELF_SOLID);
+    if (sp.on && sp.fmap[cidx(a, g)] < 0) return;  // sparse addressing stores fluid cells only
+    const double r = rho[cidx(a, g)], ux = u[cidx(a, g)], uy = u[cells(a) + cidx(a, g)], uz = u[2 * cells(a) + cidx(a, g)];
     const double usq = ux * ux + uy * uy + uz * uz;
     typename S::T *A = (typename S::T *)a.pdf;
 #pragma unroll
@@ -252,11 +265,11 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_set_pdfs(LatticeArgs a, Spar
     const int z = blockIdx.z;
     if (x >= a.nx || y >= a.ny) return;
     const Geom g = make_geom(a, x, y, z);
-    if (sp.on && sp.fmap[g.c] < 0) return;  // sparse addressing stores fluid cells only
+    if (sp.on && sp.fmap[cidx(a, g)] < 0) return;  // sparse addressing stores fluid cells only
     typename S::T *A = (typename S::T *)a.pdf;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        A[index_t0<Q>(a, sp, g, i)] = S::cvt((float)(f[(uint64_t)i * a.n + g.c] - wgt<Q>(i)));
+        A[index_t0<Q>(a, sp, g, i)] = S::cvt((float)(f[(uint64_t)i * cells(a) + cidx(a, g)] - wgt<Q>(i)));
     }
 }
 
@@ -268,7 +281,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_get_pdfs(LatticeArgs a, Spar
     const int z = blockIdx.z;
     if (x >= a.nx || y >= a.ny) return;
     const Geom g = make_geom(a, x, y, z);
-    const uint32_t m = a.mask ? a.mask[g.c] : 0u;
+    const uint32_t m = a.mask ? a.mask[cidx(a, g)] : 0u;
     float d[Q];
     if (m & SELF_SOLID) {
 #pragma unroll
@@ -277,7 +290,7 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_get_pdfs(LatticeArgs a, Spar
         load_state<Q, ST>(a, sp, g, m, odd, d);
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[(uint64_t)i * a.n + g.c] = wgt<Q>(i) + (double)d[i];
+    for (int i = 0; i < Q; ++i) f[(uint64_t)i * cells(a) + cidx(a, g)] = wgt<Q>(i) + (double)d[i];
 }
 
 template <int Q, int ST>
@@ -287,14 +300,14 @@ __global__ void __launch_bounds__(256) k_gather(LatticeArgs a, SparseArgs sp, in
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= ncell) return;
     const int64_t c = cells[r];
-    if (c < 0 || c >= (int64_t)a.n) {
+    if (c < 0 || c >= (int64_t)lbm::cells(a)) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) out[r * Q + i] = __builtin_nan("");
         return;
     }
     const int x = (int)(c % a.nx), y = (int)((c / a.nx) % a.ny), z = (int)(c / ((int64_t)a.nx * a.ny));
     const Geom g = make_geom(a, x, y, z);
-    const uint32_t m = a.mask ? a.mask[g.c] : 0u;
+    const uint32_t m = a.mask ? a.mask[cidx(a, g)] : 0u;
     float d[Q];
     if (m & SELF_SOLID) {
 #pragma unroll
@@ -314,20 +327,20 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_moments(LatticeArgs a, Spars
     const int z = blockIdx.z;
     if (x >= a.nx || y >= a.ny) return;
     const Geom g = make_geom(a, x, y, z);
-    const uint32_t m = a.mask ? a.mask[g.c] : 0u;
+    const uint32_t m = a.mask ? a.mask[cidx(a, g)] : 0u;
     if (m & SELF_SOLID) {
-        rho[g.c] = 1.f;
-        u[g.c] = u[(uint64_t)a.n + g.c] = u[2 * (uint64_t)a.n + g.c] = 0.f;
+        rho[cidx(a, g)] = 1.f;
+        u[cidx(a, g)] = u[cells(a) + cidx(a, g)] = u[2 * cells(a) + cidx(a, g)] = 0.f;
         return;
     }
     float d[Q];
     load_state<Q, ST>(a, sp, g, m, odd, d);
     float drho;
     const Macro M = moments<Q>(a, d, drho);
-    rho[g.c] = M.rho;
-    u[g.c] = M.ux;
-    u[(uint64_t)a.n + g.c] = M.uy;
-    u[2 * (uint64_t)a.n + g.c] = M.uz;
+    rho[cidx(a, g)] = M.rho;
+    u[cidx(a, g)] = M.ux;
+    u[cells(a) + cidx(a, g)] = M.uy;
+    u[2 * cells(a) + cidx(a, g)] = M.uz;
 }
 
 // Deterministic FP64 totals: each block owns a fixed slice of cells and
@@ -346,15 +359,18 @@ template <int Q, int ST>
 __global__ void __launch_bounds__(256) k_totals(LatticeArgs a, SparseArgs sp, int odd, double *partial)
 {
     double acc[5] = {0, 0, 0, 0, 0};
-    const uint32_t per_block = (a.n + TOT_BLOCKS - 1) / TOT_BLOCKS;
-    const uint32_t lo = blockIdx.x * per_block;
-    const uint32_t hi = min(a.n, lo + per_block);
-    for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
-        const int x = (int)(c % (uint32_t)a.nx);
-        const int y = (int)((c / (uint32_t)a.nx) % (uint32_t)a.ny);
-        const int z = (int)(c / ((uint32_t)a.nx * (uint32_t)a.ny));
+    const uint64_t n = cells(a);
+    const uint64_t per_block = (n + TOT_BLOCKS - 1) / TOT_BLOCKS;
+    const uint64_t lo = (uint64_t)blockIdx.x * per_block;
+    const uint64_t hi = lo + per_block < n ? lo + per_block : n;
+    const uint64_t plane = (uint64_t)a.nx * (uint64_t)a.ny;
+    for (uint64_t c = lo + threadIdx.x; c < hi; c += blockDim.x) {
+        const int z = (int)(c / plane);
+        const uint64_t r = c - (uint64_t)z * plane;
+        const int y = (int)(r / (uint64_t)a.nx);
+        const int x = (int)(r - (uint64_t)y * (uint64_t)a.nx);
         const Geom g = make_geom(a, x, y, z);
-        const uint32_t m = a.mask ? a.mask[g.c] : 0u;
+        const uint32_t m = a.mask ? a.mask[cidx(a, g)] : 0u;
         if (m & SELF_SOLID) continue;
         float d[Q];
         load_state<Q, ST>(a, sp, g, m, odd, d);
@@ -451,24 +467,25 @@ hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, 
 }
 
 template <int Q, int ST, int CL, bool MASK, int COLL>
-static void launch_sc(const LatticeArgs &a, int odd, const Launch &L, hipStream_t s)
+static void launch_sc(const LatticeArgs &a, const HrrArgs &h, int odd, const Launch &L, hipStream_t s)
 {
-    k_stream_collide<Q, ST, CL, MASK, COLL><<<L.grid, L.block, 0, s>>>(a, odd);
+    k_stream_collide<Q, ST, CL, MASK, COLL><<<L.grid, L.block, 0, s>>>(a, odd, h);
 }
 
 template <int Q, int ST, int COLL>
-static void step_coll(const LatticeArgs &a, int cl, bool mk, int odd, const Launch &L, hipStream_t s)
+static void step_coll(const LatticeArgs &a, const HrrArgs &h, int cl, bool mk, int odd, const Launch &L,
+                      hipStream_t s)
 {
     if (cl == CL_NONE) {
         if (mk)
-            launch_sc<Q, ST, CL_NONE, true, COLL>(a, odd, L, s);
+            launch_sc<Q, ST, CL_NONE, true, COLL>(a, h, odd, L, s);
         else
-            launch_sc<Q, ST, CL_NONE, false, COLL>(a, odd, L, s);
+            launch_sc<Q, ST, CL_NONE, false, COLL>(a, h, odd, L, s);
     } else {
         if (mk)
-            launch_sc<Q, ST, CL_SMAG, true, COLL>(a, odd, L, s);
+            launch_sc<Q, ST, CL_SMAG, true, COLL>(a, h, odd, L, s);
         else
-            launch_sc<Q, ST, CL_SMAG, false, COLL>(a, odd, L, s);
+            launch_sc<Q, ST, CL_SMAG, false, COLL>(a, h, odd, L, s);
     }
 }
 
@@ -496,7 +513,7 @@ static bool even_pair16(const LatticeArgs &a, int cl, int coll, hipStream_t s)
 }
 
 template <int Q, int ST>
-static hipError_t step_q_st(const LatticeArgs &a, int cl, int coll, int odd, hipStream_t s)
+static hipError_t step_q_st(const LatticeArgs &a, const HrrArgs &h, int cl, int coll, int odd, hipStream_t s)
 {
     if (!odd && even_pair16<Q, ST>(a, cl, coll, s)) return hipGetLastError();
     const Launch L = lattice_launch(a);
@@ -504,20 +521,30 @@ static hipError_t step_q_st(const LatticeArgs &a, int cl, int coll, int odd, hip
     if (cl == CL_MLP) {  // the learned closure runs with the TRT collision
         if (coll != COLL_TRT) return hipErrorInvalidValue;
         if (mk)
-            launch_sc<Q, ST, CL_MLP, true, COLL_TRT>(a, odd, L, s);
+            launch_sc<Q, ST, CL_MLP, true, COLL_TRT>(a, h, odd, L, s);
         else
-            launch_sc<Q, ST, CL_MLP, false, COLL_TRT>(a, odd, L, s);
+            launch_sc<Q, ST, CL_MLP, false, COLL_TRT>(a, h, odd, L, s);
+    } else if (coll == COLL_HRR) {  // D3Q19, no closure
+        if constexpr (Q == 19) {
+            if (cl != CL_NONE) return hipErrorInvalidValue;
+            if (mk)
+                launch_sc<Q, ST, CL_NONE, true, COLL_HRR>(a, h, odd, L, s);
+            else
+                launch_sc<Q, ST, CL_NONE, false, COLL_HRR>(a, h, odd, L, s);
+        } else {
+            return hipErrorInvalidValue;
+        }
     } else if (coll == COLL_MRT) {
-        step_coll<Q, ST, COLL_MRT>(a, cl, mk, odd, L, s);
+        step_coll<Q, ST, COLL_MRT>(a, h, cl, mk, odd, L, s);
     } else {
-        step_coll<Q, ST, COLL_TRT>(a, cl, mk, odd, L, s);
+        step_coll<Q, ST, COLL_TRT>(a, h, cl, mk, odd, L, s);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_step(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s)
+hipError_t launch_step(const LatticeArgs &a, const HrrArgs &h, int q, int st, int cl, int coll, int odd, hipStream_t s)
 {
-    return dispatch(q, st, [&](auto Q, auto ST) { return step_q_st<Q.value, ST.value>(a, cl, coll, odd, s); });
+    return dispatch(q, st, [&](auto Q, auto ST) { return step_q_st<Q.value, ST.value>(a, h, cl, coll, odd, s); });
 }
 
 hipError_t launch_init_eq(const LatticeArgs &a, const SparseArgs &sp, int q, int st, const double *rho,

@@ -178,6 +178,7 @@ hipError_t launch_step_sparse(const LatticeArgs &a, const SparseArgs &sp, int q,
                               hipStream_t s)
 {
     if (cl == CL_MLP && coll == COLL_MRT) return hipErrorInvalidValue;
+    if (coll == COLL_HRR) return hipErrorInvalidValue;  // HRR runs with the dense AA pattern only
     if (sp.nf == 0) return hipSuccess;
     const dim3 grid((sp.nf + 255) / 256);
     return dispatch(q, st, [&](auto Qc, auto STc) {

@@ -178,3 +178,35 @@ __host__ __device__ constexpr int mrt_j_axis(int a)
 }
 
 }  // namespace lbm
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Hermite polynomials of the hybrid recursive regularised collision (D3Q19).
+// Second order: H_ab = c_a c_b - c_s^2 delta_ab.  Third order: D3Q19 carries
+// the mixed polynomials H_aab only as the six sums and differences
+// T_0,1 = H_xxy +- H_yzz, T_2,3 = H_xzz +- H_xyy, T_4,5 = H_yyz +- H_xxz,
+// which are orthogonal with the lattice weights (norms 2/27 and 6/27).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr double herm3(int i, int a, int b, int g)
+{
+    return (double)(cdir(i, a) * cdir(i, b) * cdir(i, g)) -
+           (cdir(i, a) * (b == g) + cdir(i, b) * (a == g) + cdir(i, g) * (a == b)) / 3.0;
+}
+
+__host__ __device__ constexpr double t3val(int i, int k)
+{
+    constexpr int A[6][2][3] = {{{0, 0, 1}, {1, 2, 2}}, {{0, 0, 1}, {1, 2, 2}}, {{0, 2, 2}, {0, 1, 1}},
+                                {{0, 2, 2}, {0, 1, 1}}, {{1, 1, 2}, {0, 0, 2}}, {{1, 1, 2}, {0, 0, 2}}};
+    const double s = (k & 1) ? -1.0 : 1.0;
+    return herm3(i, A[k][0][0], A[k][0][1], A[k][0][2]) + s * herm3(i, A[k][1][0], A[k][1][1], A[k][1][2]);
+}
+
+__host__ __device__ constexpr double t3norm(int k)
+{
+    double s = 0.0;
+    for (int i = 0; i < 19; ++i) s += wgt<19>(i) * t3val(i, k) * t3val(i, k);
+    return s;
+}
+
+}  // namespace lbm

@@ -20,7 +20,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1,
 BC = {"periodic": 0, "noslip": 1, "velocity": 2, "pressure": 3}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 CLOSURE = {"none": 0, "smagorinsky": 1, "mlp": 2}
-COLLISION = {"trt": 0, "mrt": 1}
+COLLISION = {"trt": 0, "mrt": 1, "hrr": 2}
 STREAMING = {"aa": 0, "et": 1, "sparse": 2}
 MRT_DEFAULT_RATES = (1.19, 1.4, 1.2, 1.4, 1.98)
 MLP_NPARAM, MLP_NNORM = 1313, 24
@@ -52,6 +52,7 @@ class Domain(ctypes.Structure):
         ("storage", ctypes.c_int32), ("closure", ctypes.c_int32), ("use_flags", ctypes.c_int32),
         ("magic", ctypes.c_double), ("cs_smag", ctypes.c_double),
         ("collision", ctypes.c_int32), ("mrt_rates", ctypes.c_double * 5), ("streaming", ctypes.c_int32),
+        ("hrr_sigma", ctypes.c_double),
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
     ]
@@ -132,7 +133,7 @@ def _dev(t, dtype, device):
 
 def make_domain(shape, bc=("periodic",) * 6, u_bc=None, rho_bc=None, storage="f32", closure="none",
                 use_flags=False, magic=3.0 / 16.0, cs=0.1, collision="trt", mrt_rates=None,
-                streaming="aa") -> Domain:
+                streaming="aa", hrr_sigma=None) -> Domain:
     d = Domain()
     lib().lbm_domain_defaults(ctypes.byref(d))
     d.nx, d.ny, d.nz = (int(v) for v in shape)
@@ -153,6 +154,8 @@ def make_domain(shape, bc=("periodic",) * 6, u_bc=None, rho_bc=None, storage="f3
         for k in range(5):
             d.mrt_rates[k] = float(mrt_rates[k])
     d.streaming = STREAMING[streaming] if isinstance(streaming, str) else int(streaming)
+    if hrr_sigma is not None:
+        d.hrr_sigma = float(hrr_sigma)
     return d
 
 
@@ -174,18 +177,21 @@ class Lattice:
 
     streaming: "aa" (AA pattern), "et" (Esoteric Twist) or "sparse" (the AA
     pattern over the fluid cells only, for domains that `solid` fills to a
-    large part; the workspace is then sized by the fluid cells)."""
+    large part; the workspace is then sized by the fluid cells).
+    collision: "trt", "mrt" or "hrr" (D3Q19, AA, no closure; hrr_sigma is
+    the weight of the projected non-equilibrium flux)."""
 
     def __init__(self, shape, q: int = 19, tau: float = 0.6, force=(0.0, 0.0, 0.0), bc=("periodic",) * 6,
                  u_bc=None, rho_bc=None, solid: Optional[np.ndarray] = None, storage="f32", closure="none",
-                 magic=3.0 / 16.0, cs=0.1, collision="trt", mrt_rates=None, streaming="aa", device="cuda:0"):
+                 magic=3.0 / 16.0, cs=0.1, collision="trt", mrt_rates=None, streaming="aa", hrr_sigma=None,
+                 device="cuda:0"):
         torch = _torch()
         self.device = torch.device(device)
         self.q = int(q)
         self.shape = tuple(int(v) for v in shape)
         self.n = self.shape[0] * self.shape[1] * self.shape[2]
         self.domain = make_domain(shape, bc, u_bc, rho_bc, storage, closure, solid is not None, magic, cs,
-                                  collision, mrt_rates, streaming)
+                                  collision, mrt_rates, streaming, hrr_sigma)
         flags = None
         if solid is not None:
             self._flags = np.ascontiguousarray(solid, dtype=np.uint8).reshape(-1)

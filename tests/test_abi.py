@@ -112,10 +112,30 @@ def d_rejects(L, d):
     return L.lbm_workspace_bytes(ctypes.byref(d), 19, ctypes.byref(out)) == lbm.LBM_EINVAL
 
 
-def test_too_many_cells_is_enomem(L):
-    d = lbm.make_domain((2048, 1024, 1024))
+def test_domains_beyond_2_31_cells(L):
+    """Cell indices are 64-bit: a dense context may hold more than 2^31 (and
+    2^32) cells, up to what HBM holds, and its workspace is the plain count.
+    Sparse addressing keeps 32-bit indices: ENOMEM from 2^32 cells or 2^31
+    fluid cells.
+    The launch grid spans ny and nz: each at most 65535."""
     out = ctypes.c_size_t(0)
+    for shape in [(2048, 1024, 1025), (4096, 1024, 1025)]:  # 2^31 + 2^21 and 2^32 + 2^22 cells
+        d = lbm.make_domain(shape)
+        assert L.lbm_workspace_bytes(ctypes.byref(d), 19, ctypes.byref(out)) == lbm.LBM_OK
+        n = shape[0] * shape[1] * shape[2]
+        assert out.value >= 19 * 4 * n and out.value - 19 * 4 * n < 1 << 20
+        d16 = lbm.make_domain(shape, storage="f16")
+        assert L.lbm_workspace_bytes(ctypes.byref(d16), 19, ctypes.byref(out)) == lbm.LBM_OK
+        assert out.value >= 19 * 2 * n
+    d = lbm.make_domain((4096, 1024, 1025), streaming="sparse")
     assert L.lbm_workspace_bytes(ctypes.byref(d), 19, ctypes.byref(out)) == lbm.LBM_ENOMEM
+    # without flags every cell is fluid: fluid indices are signed 32-bit
+    d = lbm.make_domain((2048, 1024, 1025), streaming="sparse")
+    assert L.lbm_workspace_bytes(ctypes.byref(d), 19, ctypes.byref(out)) == lbm.LBM_ENOMEM
+    d = lbm.make_domain((2048, 1024, 1023), streaming="sparse")  # 2^31 - 2^21 cells
+    assert L.lbm_workspace_bytes(ctypes.byref(d), 19, ctypes.byref(out)) == lbm.LBM_OK
+    d = lbm.make_domain((8, 65536, 4))
+    assert L.lbm_workspace_bytes(ctypes.byref(d), 19, ctypes.byref(out)) == lbm.LBM_EINVAL
 
 
 def _create(L, d, q=19, tau=0.6, flags=None):
@@ -126,10 +146,24 @@ def _create(L, d, q=19, tau=0.6, flags=None):
 
 
 @pytest.mark.parametrize("case", ["tau", "pairing", "bcenum", "null_ws", "small_ws", "align", "flags", "mrt_mlp",
-                                  "sparse_small_ws"])
+                                  "sparse_small_ws", "hrr_d3q27", "hrr_et", "hrr_sparse", "hrr_closure", "hrr_sigma",
+                                  "hrr_small_ws"])
 def test_create_rejects_before_device(L, case):
     d = lbm.make_domain((8, 8, 8))
-    need = lbm.workspace_bytes(d, 19)
+    q = 19
+    if case.startswith("hrr"):
+        d.collision = lbm.COLLISION["hrr"]
+        if case == "hrr_d3q27":
+            q = 27
+        elif case == "hrr_et":
+            d.streaming = lbm.STREAMING["et"]
+        elif case == "hrr_sparse":
+            d.streaming = lbm.STREAMING["sparse"]
+        elif case == "hrr_closure":
+            d.closure = lbm.CLOSURE["smagorinsky"]
+        elif case == "hrr_sigma":
+            d.hrr_sigma = 1.5
+    need = lbm.workspace_bytes(d, q)
     d.workspace = 0x100000
     d.workspace_bytes = need
     tau = 0.6
@@ -162,9 +196,25 @@ def test_create_rejects_before_device(L, case):
         d.workspace_bytes = lbm.workspace_bytes(d, 19, half)
         buf = (ctypes.c_uint8 * 512)()
         flags = ctypes.cast(buf, ctypes.c_void_p)
-    rc, h = _create(L, d, tau=tau, flags=flags)
+    elif case == "hrr_small_ws":
+        # sized without the two velocity fields of HRR
+        d.collision = lbm.COLLISION["trt"]
+        d.workspace_bytes = lbm.workspace_bytes(d, 19)
+        d.collision = lbm.COLLISION["hrr"]
+    rc, h = _create(L, d, q=q, tau=tau, flags=flags)
     assert rc == lbm.LBM_EINVAL and not h.value
     assert len(L.lbm_last_error(None)) > 0
+
+
+def test_hrr_workspace_holds_two_velocity_fields(L):
+    """HRR keeps the previous and the current velocity field (3 FP32 each per
+    cell) next to the populations."""
+    d = lbm.make_domain((64, 32, 16))
+    trt = lbm.workspace_bytes(d, 19)
+    d.collision = lbm.COLLISION["hrr"]
+    assert lbm.workspace_bytes(d, 19) - trt == 2 * 12 * 64 * 32 * 16
+    d2 = lbm.make_domain((8, 8, 8))
+    assert d2.hrr_sigma == 0.995
 
 
 def test_free_functions_reject(L):
