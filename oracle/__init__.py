@@ -22,7 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 MLP_NPARAM = 1313
 MLP_NNORM = 24
 
-BC_PERIODIC, BC_NOSLIP, BC_VELOCITY, BC_PRESSURE = 0, 1, 2, 3
+BC_PERIODIC, BC_NOSLIP, BC_VELOCITY, BC_PRESSURE, BC_INTERFACE = 0, 1, 2, 3, 4
 CL_NONE, CL_SMAG, CL_MLP = 0, 1, 2
 
 
@@ -85,6 +85,7 @@ def lib():
         L.orc_collide_hrr.argtypes = [_D, ctypes.c_double, ctypes.c_double, _D, _D, _D]
         L.orc_fd_gradient.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.orc_refine_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
         L.orc_moments.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_totals.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_probe.argtypes = [ctypes.c_void_p, _D, _D, ctypes.c_int, ctypes.c_int64, _I64, _D]
@@ -247,6 +248,16 @@ def closure_dataset(filt, periodic, tau, cs=0.1, eps=1e-30):
     lib().orc_closure_dataset(cx, cy, cz, per.ctypes.data_as(_I), _d(filt), float(tau), float(cs), float(eps),
                               _d(x), _d(t))
     return x, t
+
+
+def refine_step(coarse, fine_lo=None, fine_hi=None, n=1):
+    """Advance a 2:1 refinement: the coarse Sim n steps and the fine Sims
+    (below its -y face / above its +y face, nullable) 2n steps, exchanging the
+    packets that cross the BC_INTERFACE faces."""
+    lo = fine_lo._h if fine_lo is not None else None
+    hi = fine_hi._h if fine_hi is not None else None
+    if lib().orc_refine_step(coarse._h, lo, hi, int(n)) != 0:
+        raise ValueError("these lattices do not form a 2:1 refinement")
 
 
 class Sim:

@@ -505,7 +505,9 @@ int orc_hrr_norms(double *norm)
 /* ------------------------------------------------------------------------ */
 /* Simulation state.                                                         */
 /* ------------------------------------------------------------------------ */
-enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
+/* BC_INTERFACE: a face of a 2:1 refinement interface (orc_refine_step); within */
+/* one lattice it returns populations as a no-slip face does.                  */
+enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_VELOCITY = 2, BC_PRESSURE = 3, BC_INTERFACE = 4 };
 
 typedef struct {
     int q, nx, ny, nz;
@@ -828,7 +830,7 @@ static double push_target(const orc_sim *s, int x, int y, int z, int i, double v
     int p[3] = {x + VEL[i][0], y + VEL[i][1], z + VEL[i][2]};
     int ext[3] = {s->nx, s->ny, s->nz};
     int cut_kind = -1, cut_face = -1;
-    static const int rank_of[4] = {0, 3, 2, 1}; /* precedence: no-slip > velocity > pressure */
+    static const int rank_of[5] = {0, 3, 2, 1, 3}; /* precedence: no-slip (interface) > velocity > pressure */
     for (int a = 0; a < 3; ++a) {
         int face = -1;
         if (p[a] < 0) face = 2 * a;
@@ -854,7 +856,7 @@ static double push_target(const orc_sim *s, int x, int y, int z, int i, double v
     *tgt = self;
     *dir = opposite(i);
     double w = weight(s->q, i);
-    if (cut_kind == BC_NOSLIP) return v;
+    if (cut_kind == BC_NOSLIP || cut_kind == BC_INTERFACE) return v;
     if (cut_kind == BC_VELOCITY) {
         const double *uw = s->ubc[cut_face];
         double cuw = VEL[i][0] * uw[0] + VEL[i][1] * uw[1] + VEL[i][2] * uw[2];
@@ -1045,6 +1047,171 @@ void orc_step(orc_sim *s, int64_t nsteps)
         }
     }
     free(unext);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2:1 grid refinement (the block forest's 2:1 refinement, Section 3; the     */
+/* coarse-to-fine and fine-to-coarse kernels of the LAGOON runs, Section 5.2). */
+/* The paper gives no algorithm; this is the mass-conservative volumetric     */
+/* scheme of Rohde, Kandhai, Derksen & van den Akker (2006): coarse packets   */
+/* spread evenly over the fine cells they enter ("explosion"), fine packets   */
+/* summed into the coarse cell they enter ("coalescence").                   */
+/* A coarse lattice and fine lattices below (its -y face) and/or above (its   */
+/* +y face), each fine lattice twice as fine in every direction (nx, nz       */
+/* twice the coarse ones, x and z periodic on every level), the fine         */
+/* relaxation time 1/2 + 2 (tau_c - 1/2) and force F_c / 2 (acoustic         */
+/* scaling: the same viscosity and acceleration in physical units).  The      */
+/* faces between the levels are BC_INTERFACE faces: within a lattice they     */
+/* return each population into the emitting cell (as no-slip faces do), and   */
+/* the packets that crossed are exchanged between steps, populations read as  */
+/* mass densities (a fine cell holds 1/8 of a coarse cell's volume):          */
+/*   coarse to fine: the packet f*_i a coarse interface cell X sends across   */
+/*     in coarse step t -> t+1 (canonical f_opp(i)(X) after that step)        */
+/*     enters the fine level over both fine substeps: after each substep,    */
+/*     every fine interface cell whose source point x_f - c_i (fine units)    */
+/*     lies in X takes it as its population i (four fine cells per substep:   */
+/*     mass 2 x 4 x f / 8 = f).  The first substep of the next coarse step    */
+/*     therefore collides the second half of this step's packets.             */
+/*   fine to coarse: the packets f*_i the fine interface cells send across in  */
+/*     the two substeps (canonical f_opp(i)(x_f) after each) are summed over  */
+/*     the fine cells whose target point x_f + c_i lies in coarse cell Y,     */
+/*     divided by 8, and arrive in Y as its population i at t+1.              */
+/* Order per coarse step: coarse step; record the coarse packets; twice: fine  */
+/* step, add the fine packets, fine interface row from the recorded packets;   */
+/* coarse interface row from the sums.  Between steps every slot holds mass  */
+/* that belongs to its level, so M_c + M_f / 8 is conserved exactly.  The     */
+/* even spreading makes the interface first-order accurate (the levels are    */
+/* second order); force-driven channel flow across it stays exact.            */
+/* Interface rows hold no solid cells; TRT or MRT (same ghost rates), no       */
+/* closure, no HRR.  Pinned by a brute-force emulation of the exchange, exact  */
+/* mass conservation, invariance of a uniform moving state, the exact         */
+/* force-driven channel across both interfaces and first-order convergence   */
+/* to a run that is fine everywhere (tests).                                  */
+/* ------------------------------------------------------------------------ */
+static int64_t wrapi(int64_t v, int64_t n) { return ((v % n) + n) % n; }
+
+/* Refinement geometry check; returns 0 if coarse/fine fit (fine on side     */
+/* `above` of the coarse lattice).                                           */
+static int refine_pair_ok(const orc_sim *c, const orc_sim *f, int above)
+{
+    if (!f) return 0;
+    if (f->q != c->q || f->nx != 2 * c->nx || f->nz != 2 * c->nz) return -1;
+    if (c->bc[0] != BC_PERIODIC || c->bc[4] != BC_PERIODIC || f->bc[0] != BC_PERIODIC || f->bc[4] != BC_PERIODIC)
+        return -1;
+    if (c->bc[above ? 3 : 2] != BC_INTERFACE || f->bc[above ? 2 : 3] != BC_INTERFACE) return -1;
+    if (fabs(f->tau - (0.5 + 2.0 * (c->tau - 0.5))) > 1e-12 * c->tau) return -1;
+    /* TRT or MRT (same ghost rates) without a closure: HRR's gradient would  */
+    /* span the levels, and a closure's scaling between levels is not defined */
+    if (c->collision != f->collision || c->collision == 2 || c->closure || f->closure) return -1;
+    if (c->collision == 1)
+        for (int k = 0; k < 5; ++k)
+            if (c->mrt_rates[k] != f->mrt_rates[k]) return -1;
+    if (c->magic != f->magic) return -1;
+    int yc = above ? c->ny - 1 : 0, yf = above ? 0 : f->ny - 1;
+    for (int z = 0; z < c->nz; ++z)
+        for (int x = 0; x < c->nx; ++x)
+            if (is_solid(c, cell_index(c, x, yc, z))) return -1;
+    for (int z = 0; z < f->nz; ++z)
+        for (int x = 0; x < f->nx; ++x)
+            if (is_solid(f, cell_index(f, x, yf, z))) return -1;
+    for (int a = 0; a < 3; ++a)
+        if (fabs(f->F[a] - 0.5 * c->F[a]) > 1e-15 + 1e-12 * fabs(c->F[a])) return -1;
+    return 0;
+}
+
+/* One interface: coarse row yc of the coarse lattice, fine row yf of the    */
+/* fine lattice; dy = +1 if the fine lattice lies above (coarse packets      */
+/* toward the fine level have c_y = dy).  cout, acc: [q][nzc][nxc].          */
+static void refine_record_coarse(const orc_sim *c, int yc, int dy, double *cout)
+{
+    int64_t N = c->n, plane = (int64_t)c->nx * c->nz;
+    for (int i = 0; i < c->q; ++i) {
+        if (VEL[i][1] != dy) continue;
+        for (int z = 0; z < c->nz; ++z)
+            for (int x = 0; x < c->nx; ++x)
+                cout[i * plane + (int64_t)z * c->nx + x] = c->f[opposite(i) * N + cell_index(c, x, yc, z)];
+    }
+}
+
+/* Fine interface row after a fine substep: fine cell x_f takes, as its     */
+/* population j, the packet of the coarse cell containing its source point   */
+/* x_f - c_j (fine units).                                                   */
+static void refine_fill_fine(orc_sim *f, const orc_sim *c, int yf, int dy, const double *cout)
+{
+    int64_t N = f->n, plane = (int64_t)c->nx * c->nz;
+    for (int j = 0; j < f->q; ++j) {
+        if (VEL[j][1] != dy) continue;
+        for (int z = 0; z < f->nz; ++z)
+            for (int x = 0; x < f->nx; ++x) {
+                int64_t px = wrapi(x - VEL[j][0], f->nx) / 2, pz = wrapi(z - VEL[j][2], f->nz) / 2;
+                f->f[j * N + cell_index(f, x, yf, z)] = cout[j * plane + pz * c->nx + px];
+            }
+    }
+}
+
+/* Fine packets sent across in a substep: 1/8 of each goes to the coarse     */
+/* cell containing the target point x_f + c_i (fine units); the first       */
+/* substep clears the sums.                                                 */
+static void refine_add_fine(const orc_sim *f, const orc_sim *c, int yf, int dy, double *acc, int first)
+{
+    int64_t N = f->n, plane = (int64_t)c->nx * c->nz;
+    for (int i = 0; i < f->q; ++i) {
+        if (VEL[i][1] != -dy) continue;
+        if (first)
+            for (int64_t k = 0; k < plane; ++k) acc[i * plane + k] = 0.0;
+        for (int z = 0; z < f->nz; ++z)
+            for (int x = 0; x < f->nx; ++x) {
+                int64_t yx = wrapi(x + VEL[i][0], f->nx) / 2, yz = wrapi(z + VEL[i][2], f->nz) / 2;
+                acc[i * plane + yz * c->nx + yx] += f->f[opposite(i) * N + cell_index(f, x, yf, z)] / 8.0;
+            }
+    }
+}
+
+static void refine_fill_coarse(orc_sim *c, int yc, int dy, const double *acc)
+{
+    int64_t N = c->n, plane = (int64_t)c->nx * c->nz;
+    for (int i = 0; i < c->q; ++i) {
+        if (VEL[i][1] != -dy) continue;
+        for (int z = 0; z < c->nz; ++z)
+            for (int x = 0; x < c->nx; ++x)
+                c->f[i * N + cell_index(c, x, yc, z)] = acc[i * plane + (int64_t)z * c->nx + x];
+    }
+}
+
+/* Advance the coarse lattice n steps and each fine lattice (nullable)      */
+/* 2n steps.  Returns -1 if the lattices do not form a refinement.          */
+int orc_refine_step(orc_sim *c, orc_sim *fine_lo, orc_sim *fine_hi, int64_t n)
+{
+    if (refine_pair_ok(c, fine_lo, 0) || refine_pair_ok(c, fine_hi, 1)) return -1;
+    if ((c->bc[2] == BC_INTERFACE) != (fine_lo != 0) || (c->bc[3] == BC_INTERFACE) != (fine_hi != 0)) return -1;
+    orc_sim *fl[2] = {fine_lo, fine_hi};
+    int64_t plane = (int64_t)c->nx * c->nz;
+    double *buf = (double *)calloc((size_t)(4 * c->q * plane), sizeof(double));
+    ensure_lattices(c);
+    for (int k = 0; k < 2; ++k)
+        if (fl[k]) ensure_lattices(fl[k]);
+    for (int64_t t = 0; t < n; ++t) {
+        orc_step(c, 1);
+        for (int k = 0; k < 2; ++k) {
+            orc_sim *f = fl[k];
+            if (!f) continue;
+            int dy = k ? 1 : -1, yc = k ? c->ny - 1 : 0, yf = k ? 0 : f->ny - 1;
+            double *cout = buf + (int64_t)(2 * k) * c->q * plane, *acc = cout + (int64_t)c->q * plane;
+            refine_record_coarse(c, yc, dy, cout);
+            for (int sub = 0; sub < 2; ++sub) {
+                orc_step(f, 1);
+                refine_add_fine(f, c, yf, dy, acc, sub == 0);
+                refine_fill_fine(f, c, yf, dy, cout);
+            }
+        }
+        for (int k = 0; k < 2; ++k) {
+            if (!fl[k]) continue;
+            int dy = k ? 1 : -1, yc = k ? c->ny - 1 : 0;
+            refine_fill_coarse(c, yc, dy, buf + (int64_t)(2 * k + 1) * c->q * plane);
+        }
+    }
+    free(buf);
+    return 0;
 }
 
 /* Density and velocity u = (j + F/2)/rho of the canonical state; u [3][n]. */
