@@ -66,7 +66,10 @@ enum {
     LBM_BC_PERIODIC = 0, /* wrap around; the opposite face must be periodic too */
     LBM_BC_NOSLIP = 1,   /* halfway bounce-back */
     LBM_BC_VELOCITY = 2, /* moving-wall bounce-back with u_bc and rho_bc of the face */
-    LBM_BC_PRESSURE = 3  /* anti-bounce-back with density rho_bc of the face */
+    LBM_BC_PRESSURE = 3, /* anti-bounce-back with density rho_bc of the face */
+    LBM_BC_INTERFACE = 4 /* a face of a 2:1 refinement interface (-y or +y only; the dense
+                            AA pattern, no HRR): steps of this lattice alone treat it as
+                            no-slip; lbm_refine_step exchanges the packets that cross it */
 };
 
 /* Population storage in HBM.  All forms store the deviation f_i - w_i. */
@@ -335,6 +338,45 @@ int lbm_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *
  * device analogue of the STREAM copy the paper uses to measure the machine
  * bandwidth b_s of its roofline P_max = b_s / n_b (Section 5.2, Eq. (3)). */
 int lbm_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, void *stream);
+
+/* 2:1 grid refinement (the paper's 2:1 block refinement, Section 3, whose
+ * levels coarse-to-fine and fine-to-coarse kernels join, Section 5.2), read
+ * as the volumetric, mass-conservative exchange of Rohde et al. (2006).
+ *
+ * A coarse lattice and fine lattices below it (fine_lo: its +y face meets
+ * the coarse -y face) and/or above it (fine_hi: its -y face meets the coarse
+ * +y face).  Every face between two levels has kind LBM_BC_INTERFACE; every
+ * other y face is not an interface.  Each fine lattice has twice the coarse
+ * nx and nz, x and z are periodic on every level, and the levels share the
+ * stencil, the collision (TRT or MRT with equal ghost rates and magic
+ * parameter), no closure, the dense AA pattern and the HIP stream.  Acoustic
+ * scaling: tau_f = 1/2 + 2 (tau_c - 1/2), force_f = force_c / 2 (relative
+ * tolerance 1e-9).  Interface rows hold no solid cells (lbm_create rejects
+ * flags there).  Storage formats may differ between levels.
+ *
+ * Per coarse step: one coarse step; each fine level takes two steps.  The
+ * packet f*_i a coarse interface cell X sends across enters the fine level
+ * after each fine substep, in the fine interface cells whose source point
+ * x_f - c_i (fine units) lies in X; the packets the fine interface cells
+ * send across in the two substeps are summed over the cells whose target
+ * point x_f + c_i lies in coarse cell Y, divided by 8 (the volume ratio),
+ * and become Y's populations.  sum_coarse rho + sum_fine rho / 8 is
+ * conserved exactly.  Between calls every slot holds mass of its level:
+ * the fine interface row's populations from the coarse level are the
+ * second half of the last coarse step's packets.
+ *
+ * lbm_refine_work_bytes: bytes of the work buffer for a coarse domain (FP32
+ * planes [2][2][q][nz][nx]).  LBM_EINVAL for NULL or a bad stencil. */
+int lbm_refine_work_bytes(const lbm_domain *coarse, int stencil, size_t *bytes);
+
+/* Advance the coarse lattice n >= 0 steps and each fine lattice 2n steps.
+ * fine_lo / fine_hi may be NULL where the coarse face is not an interface.
+ * work_dev: device buffer of at least lbm_refine_work_bytes (caller owned,
+ * 4-byte aligned).  Asynchronous, on the shared stream.  LBM_EINVAL when
+ * the lattices do not form a refinement as stated above, for a NULL or
+ * small work buffer or n < 0; LBM_EDEVICE when a launch fails. */
+int lbm_refine_step(lbm_ctx *coarse, lbm_ctx *fine_lo, lbm_ctx *fine_hi, void *work_dev, size_t work_bytes,
+                    int64_t n);
 
 #ifdef __cplusplus
 }

@@ -36,6 +36,8 @@ struct lbm_ctx {
     float *uvel[2];  // HRR velocity fields: step t reads uvel[t & 1], writes uvel[(t + 1) & 1]
     float hrr_sigma;
     int q, st, cl, coll;
+    int bc_kind[6];                           // the domain's face kinds (LBM_BC_INTERFACE kept)
+    double tau_d, force_d[3], magic_d, mrt_d[5];  // the parameters as given (refinement checks)
     int64_t time;
     hipStream_t stream;
     char *ws;
@@ -216,9 +218,29 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     if (!(tau > 0.5) || !isfinite(tau)) return fail(nullptr, LBM_EINVAL, "tau must be > 1/2 (got %g)", tau);
     if (!(d->magic > 0.0) || !isfinite(d->magic)) return fail(nullptr, LBM_EINVAL, "magic must be > 0");
     if (d->closure != LBM_LES_NONE && !(d->cs_smag >= 0.0)) return fail(nullptr, LBM_EINVAL, "cs_smag must be >= 0");
-    for (int f = 0; f < 6; ++f)
-        if (d->bc[f] < LBM_BC_PERIODIC || d->bc[f] > LBM_BC_PRESSURE)
+    bool iface = false;
+    for (int f = 0; f < 6; ++f) {
+        if (d->bc[f] < LBM_BC_PERIODIC || d->bc[f] > LBM_BC_INTERFACE)
             return fail(nullptr, LBM_EINVAL, "unknown boundary kind %d on face %d", d->bc[f], f);
+        if (d->bc[f] == LBM_BC_INTERFACE) {
+            if (f != 2 && f != 3) return fail(nullptr, LBM_EINVAL, "refinement interfaces are -y or +y faces (face %d)", f);
+            iface = true;
+        }
+    }
+    if (iface) {
+        if (d->streaming != LBM_STREAM_AA)
+            return fail(nullptr, LBM_EINVAL, "refinement interfaces need the dense AA pattern");
+        if (d->collision == LBM_COLL_HRR) return fail(nullptr, LBM_EINVAL, "refinement interfaces do not run with HRR");
+        if (flags)
+            for (int f = 2; f <= 3; ++f) {
+                if (d->bc[f] != LBM_BC_INTERFACE) continue;
+                const int64_t y = f == 2 ? 0 : d->ny - 1;
+                for (int64_t z = 0; z < d->nz; ++z)
+                    for (int64_t x = 0; x < d->nx; ++x)
+                        if (flags[(z * d->ny + y) * d->nx + x])
+                            return fail(nullptr, LBM_EINVAL, "solid cell in the interface row of face %d", f);
+            }
+    }
     for (int a = 0; a < 3; ++a)
         if ((d->bc[2 * a] == LBM_BC_PERIODIC) != (d->bc[2 * a + 1] == LBM_BC_PERIODIC))
             return fail(nullptr, LBM_EINVAL, "axis %d: a periodic face needs a periodic opposite face", a);
@@ -253,6 +275,11 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     c->st = d->storage;
     c->cl = d->closure;
     c->coll = d->collision;
+    for (int f = 0; f < 6; ++f) c->bc_kind[f] = d->bc[f];
+    c->tau_d = tau;
+    for (int k = 0; k < 3; ++k) c->force_d[k] = force ? force[k] : 0.0;
+    c->magic_d = d->magic;
+    for (int k = 0; k < 5; ++k) c->mrt_d[k] = d->mrt_rates[k];
     c->stream = (hipStream_t)d->stream;
     c->ws = (char *)d->workspace;
     c->ws_bytes = d->workspace_bytes;
@@ -285,7 +312,8 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     for (int k = 0; k < 3; ++k) a.per[k] = d->bc[2 * k] == LBM_BC_PERIODIC;
     a.any_vp = 0;
     for (int f = 0; f < 6; ++f) {
-        a.bc[f] = d->bc[f];
+        // an interface face is a no-slip face for the lattice's own steps
+        a.bc[f] = d->bc[f] == LBM_BC_INTERFACE ? LBM_BC_NOSLIP : d->bc[f];
         if (d->bc[f] == LBM_BC_VELOCITY || d->bc[f] == LBM_BC_PRESSURE) a.any_vp = 1;
         for (int k = 0; k < 3; ++k) a.ubc[f][k] = (float)d->u_bc[f][k];
         a.rhobc[f] = (float)d->rho_bc[f];
@@ -418,6 +446,17 @@ static HrrArgs hrr_args(const lbm_ctx *c, int odd)
     return h;
 }
 
+static int step_once(lbm_ctx *c)
+{
+    const int odd = (int)(c->time & 1);
+    hipError_t e = c->sp.on  ? launch_step_sparse(c->a, c->sp, c->q, c->st, c->cl, c->coll, odd, c->stream)
+                   : c->a.et ? launch_step_et(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream)
+                             : launch_step(c->a, hrr_args(c, odd), c->q, c->st, c->cl, c->coll, odd, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "stream_collide launch");
+    ++c->time;
+    return LBM_OK;
+}
+
 int lbm_step(lbm_ctx *c, int64_t n)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
@@ -425,12 +464,8 @@ int lbm_step(lbm_ctx *c, int64_t n)
     if (c->cl == LBM_LES_MLP && !c->mlp_ready)
         return fail(c, LBM_ESTATE, "MLP closure selected but lbm_set_closure_weights was not called");
     for (int64_t k = 0; k < n; ++k) {
-        const int odd = (int)(c->time & 1);
-        hipError_t e = c->sp.on  ? launch_step_sparse(c->a, c->sp, c->q, c->st, c->cl, c->coll, odd, c->stream)
-                       : c->a.et ? launch_step_et(c->a, c->q, c->st, c->cl, c->coll, odd, c->stream)
-                                 : launch_step(c->a, hrr_args(c, odd), c->q, c->st, c->cl, c->coll, odd, c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "stream_collide launch");
-        ++c->time;
+        const int rc = step_once(c);
+        if (rc) return rc;
     }
     return LBM_OK;
 }
@@ -592,6 +627,103 @@ int lbm_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, void *stre
         return fail(nullptr, LBM_EINVAL, "copy: src and dst must be 16-byte aligned");
     hipError_t e = launch_copy(src_dev, dst_dev, bytes, (hipStream_t)stream);
     return e == hipSuccess ? LBM_OK : hip_fail(nullptr, e, "stream_copy");
+}
+
+// ---------------------------------------------------------------------------
+// 2:1 grid refinement
+// ---------------------------------------------------------------------------
+static size_t refine_plane_floats(int q, int64_t nx, int64_t nz) { return (size_t)q * (size_t)nx * (size_t)nz; }
+
+int lbm_refine_work_bytes(const lbm_domain *d, int stencil, size_t *bytes)
+{
+    if (!d || !bytes) return fail(nullptr, LBM_EINVAL, "refine_work_bytes: NULL pointer");
+    if (stencil != 19 && stencil != 27) return fail(nullptr, LBM_EINVAL, "stencil must be 19 or 27, got %d", stencil);
+    if (d->nx < 1 || d->nz < 1) return fail(nullptr, LBM_EINVAL, "domain sizes must be >= 1");
+    *bytes = 4 * refine_plane_floats(stencil, d->nx, d->nz) * sizeof(float);
+    return LBM_OK;
+}
+
+static bool rel_close(double a, double b) { return fabs(a - b) <= 1e-9 * fmax(fabs(a), fabs(b)) + 1e-300; }
+
+// Does fine lattice f fit coarse lattice c on side `above`?  Writes the
+// reason into c's error text.
+static int refine_check(lbm_ctx *c, const lbm_ctx *f, int above)
+{
+    const char *side = above ? "fine_hi" : "fine_lo";
+    if (f->q != c->q) return fail(c, LBM_EINVAL, "refine: %s has another stencil", side);
+    if (f->a.nx != 2 * c->a.nx || f->a.nz != 2 * c->a.nz)
+        return fail(c, LBM_EINVAL, "refine: %s must have twice the coarse nx and nz (%d x %d, coarse %d x %d)", side,
+                    f->a.nx, f->a.nz, c->a.nx, c->a.nz);
+    if (f->bc_kind[above ? 2 : 3] != LBM_BC_INTERFACE)
+        return fail(c, LBM_EINVAL, "refine: the %s face of %s facing the coarse lattice is not an interface", above ? "-y" : "+y",
+                    side);
+    if (f->bc_kind[above ? 3 : 2] == LBM_BC_INTERFACE)
+        return fail(c, LBM_EINVAL, "refine: %s has a second interface face", side);
+    if (!f->a.per[0] || !f->a.per[2]) return fail(c, LBM_EINVAL, "refine: x and z must be periodic on %s", side);
+    if (f->sp.on || f->a.et) return fail(c, LBM_EINVAL, "refine: %s must use the dense AA pattern", side);
+    if (f->coll != c->coll) return fail(c, LBM_EINVAL, "refine: %s has another collision", side);
+    if (f->cl != LBM_LES_NONE) return fail(c, LBM_EINVAL, "refine: %s has a closure", side);
+    if (f->magic_d != c->magic_d) return fail(c, LBM_EINVAL, "refine: %s has another magic parameter", side);
+    if (c->coll == LBM_COLL_MRT)
+        for (int k = 0; k < 5; ++k)
+            if (f->mrt_d[k] != c->mrt_d[k]) return fail(c, LBM_EINVAL, "refine: %s has other MRT ghost rates", side);
+    if (!rel_close(f->tau_d, 0.5 + 2.0 * (c->tau_d - 0.5)))
+        return fail(c, LBM_EINVAL, "refine: %s needs tau = 1/2 + 2 (tau_c - 1/2) = %.17g (got %.17g)", side,
+                    0.5 + 2.0 * (c->tau_d - 0.5), f->tau_d);
+    for (int k = 0; k < 3; ++k)
+        if (!(rel_close(f->force_d[k], 0.5 * c->force_d[k]) || (f->force_d[k] == 0.0 && c->force_d[k] == 0.0)))
+            return fail(c, LBM_EINVAL, "refine: %s needs force = coarse force / 2", side);
+    if (f->stream != c->stream) return fail(c, LBM_EINVAL, "refine: %s runs on another stream", side);
+    if (f == c) return fail(c, LBM_EINVAL, "refine: %s is the coarse lattice", side);
+    return LBM_OK;
+}
+
+int lbm_refine_step(lbm_ctx *c, lbm_ctx *lo, lbm_ctx *hi, void *work_dev, size_t work_bytes, int64_t n)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "refine: coarse context is NULL");
+    if (n < 0) return fail(c, LBM_EINVAL, "refine: step count must be >= 0");
+    if ((c->bc_kind[2] == LBM_BC_INTERFACE) != (lo != nullptr) || (c->bc_kind[3] == LBM_BC_INTERFACE) != (hi != nullptr))
+        return fail(c, LBM_EINVAL, "refine: a fine lattice is given exactly where the coarse y face is an interface");
+    if (!lo && !hi) return fail(c, LBM_EINVAL, "refine: no fine lattice");
+    if (lo && hi && lo == hi) return fail(c, LBM_EINVAL, "refine: fine_lo and fine_hi are the same lattice");
+    if (!c->a.per[0] || !c->a.per[2]) return fail(c, LBM_EINVAL, "refine: x and z must be periodic on the coarse lattice");
+    if (c->sp.on || c->a.et) return fail(c, LBM_EINVAL, "refine: the coarse lattice must use the dense AA pattern");
+    if (c->cl != LBM_LES_NONE) return fail(c, LBM_EINVAL, "refine: the coarse lattice has a closure");
+    if (c->coll == LBM_COLL_HRR) return fail(c, LBM_EINVAL, "refine: HRR is not supported");
+    int rc;
+    if (lo && (rc = refine_check(c, lo, 0))) return rc;
+    if (hi && (rc = refine_check(c, hi, 1))) return rc;
+    const size_t plane = refine_plane_floats(c->q, c->a.nx, c->a.nz);
+    if (!work_dev) return fail(c, LBM_EINVAL, "refine: work buffer is NULL");
+    if (((uintptr_t)work_dev & 3) != 0) return fail(c, LBM_EINVAL, "refine: work buffer must be 4-byte aligned");
+    if (work_bytes < 4 * plane * sizeof(float))
+        return fail(c, LBM_EINVAL, "refine: work buffer too small: %zu < %zu bytes", work_bytes, 4 * plane * sizeof(float));
+    float *buf = (float *)work_dev;
+    lbm_ctx *fl[2] = {lo, hi};
+    for (int64_t t = 0; t < n; ++t) {
+        if ((rc = step_once(c))) return rc;
+        for (int k = 0; k < 2; ++k) {
+            lbm_ctx *f = fl[k];
+            if (!f) continue;
+            const int dy = k ? 1 : -1, yc = k ? c->a.ny - 1 : 0, yf = k ? 0 : f->a.ny - 1;
+            float *cout = buf + (size_t)(2 * k) * plane, *acc = cout + plane;
+            HIPCHECK(c, launch_refine_record(c->a, c->q, c->st, yc, dy, cout, c->stream), "refine record");
+            for (int sub = 0; sub < 2; ++sub) {
+                if ((rc = step_once(f))) return fail(c, rc, "refine: fine step: %s", f->err);
+                HIPCHECK(c, launch_refine_add(f->a, f->q, f->st, yf, dy, c->a.nx, c->a.nz, sub == 0, acc, c->stream),
+                         "refine add");
+                HIPCHECK(c, launch_refine_fill_fine(f->a, f->q, f->st, yf, dy, c->a.nx, c->a.nz, cout, c->stream),
+                         "refine fill fine");
+            }
+        }
+        for (int k = 0; k < 2; ++k) {
+            if (!fl[k]) continue;
+            const int dy = k ? 1 : -1, yc = k ? c->a.ny - 1 : 0;
+            HIPCHECK(c, launch_refine_fill_coarse(c->a, c->q, c->st, yc, dy, buf + (size_t)(2 * k + 1) * plane, c->stream),
+                     "refine fill coarse");
+        }
+    }
+    return LBM_OK;
 }
 
 }  // extern "C"

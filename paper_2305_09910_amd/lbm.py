@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
-BC = {"periodic": 0, "noslip": 1, "velocity": 2, "pressure": 3}
+BC = {"periodic": 0, "noslip": 1, "velocity": 2, "pressure": 3, "interface": 4}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 CLOSURE = {"none": 0, "smagorinsky": 1, "mlp": 2}
 COLLISION = {"trt": 0, "mrt": 1, "hrr": 2}
@@ -33,7 +33,7 @@ EXPORTED = [
     "lbm_moments", "lbm_totals", "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
     "lbm_set_closure_weights", "lbm_closure_fallbacks", "lbm_box_filter4", "lbm_closure_dataset",
     "lbm_mlp_forward", "lbm_mlp_work_bytes", "lbm_mlp_loss_grad", "lbm_mlp_loss_grad_noalloc", "lbm_mlp_adam",
-    "lbm_stream_copy",
+    "lbm_stream_copy", "lbm_refine_work_bytes", "lbm_refine_step",
 ]
 
 
@@ -98,6 +98,8 @@ def lib():
             "lbm_mlp_loss_grad_noalloc": (ctypes.c_int, [P, P, P, I64, P, P, P]),
             "lbm_mlp_adam": (ctypes.c_int, [P, P, P, P, I64, D, D, D, D, P]),
             "lbm_stream_copy": (ctypes.c_int, [P, P, SZ, P]),
+            "lbm_refine_work_bytes": (ctypes.c_int, [DP, ctypes.c_int, ctypes.POINTER(SZ)]),
+            "lbm_refine_step": (ctypes.c_int, [P, P, P, P, SZ, I64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -372,3 +374,20 @@ def stream_copy(src, dst, stream=None):
     nbytes = src.numel() * src.element_size()
     s = stream if stream is not None else _stream_ptr(src.device)
     _check(lib().lbm_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, s))
+
+
+def refine_step(coarse, fine_lo=None, fine_hi=None, n=1):
+    """lbm_refine_step: advance a 2:1 refinement -- the coarse Lattice n steps
+    and each fine Lattice (below / above it, None where the coarse y face is
+    not an "interface" face) 2n steps, exchanging the packets that cross the
+    interfaces.  The work buffer is allocated once per coarse lattice."""
+    torch = _torch()
+    work = getattr(coarse, "_refine_work", None)
+    if work is None:
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().lbm_refine_work_bytes(ctypes.byref(coarse.domain), coarse.q, ctypes.byref(nbytes)))
+        work = torch.empty(nbytes.value, dtype=torch.uint8, device=coarse.device)
+        coarse._refine_work = work
+    lo = fine_lo._h if fine_lo is not None else None
+    hi = fine_hi._h if fine_hi is not None else None
+    _check(lib().lbm_refine_step(coarse._h, lo, hi, work.data_ptr(), work.numel(), int(n)), coarse._h)

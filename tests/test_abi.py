@@ -147,7 +147,8 @@ def _create(L, d, q=19, tau=0.6, flags=None):
 
 @pytest.mark.parametrize("case", ["tau", "pairing", "bcenum", "null_ws", "small_ws", "align", "flags", "mrt_mlp",
                                   "sparse_small_ws", "hrr_d3q27", "hrr_et", "hrr_sparse", "hrr_closure", "hrr_sigma",
-                                  "hrr_small_ws"])
+                                  "hrr_small_ws", "bcenum5", "iface_x", "iface_et", "iface_sparse", "iface_hrr",
+                                  "iface_solid_row"])
 def test_create_rejects_before_device(L, case):
     d = lbm.make_domain((8, 8, 8))
     q = 19
@@ -201,9 +202,47 @@ def test_create_rejects_before_device(L, case):
         d.collision = lbm.COLLISION["trt"]
         d.workspace_bytes = lbm.workspace_bytes(d, 19)
         d.collision = lbm.COLLISION["hrr"]
+    elif case == "bcenum5":
+        d.bc[2] = d.bc[3] = 5
+    elif case.startswith("iface"):
+        d.bc[2], d.bc[3] = lbm.BC["interface"], lbm.BC["noslip"]
+        if case == "iface_x":
+            d.bc[2] = d.bc[3] = 0
+            d.bc[0], d.bc[1] = lbm.BC["interface"], lbm.BC["noslip"]
+        elif case == "iface_et":
+            d.streaming = lbm.STREAMING["et"]
+        elif case == "iface_sparse":
+            d.streaming = lbm.STREAMING["sparse"]
+        elif case == "iface_hrr":
+            d.collision = lbm.COLLISION["hrr"]
+        elif case == "iface_solid_row":
+            # one solid cell in the interface row y = 0 (cells [z][y][x])
+            d.use_flags = 1
+            solid = np.zeros((8, 8, 8), np.uint8)
+            solid[3, 0, 5] = 1
+            d.workspace_bytes = lbm.workspace_bytes(d, 19, solid.reshape(-1))
+            buf = (ctypes.c_uint8 * 512).from_buffer_copy(solid.tobytes())
+            flags = ctypes.cast(buf, ctypes.c_void_p)
+        if case != "iface_solid_row":
+            d.workspace_bytes = lbm.workspace_bytes(d, q)
     rc, h = _create(L, d, q=q, tau=tau, flags=flags)
     assert rc == lbm.LBM_EINVAL and not h.value
     assert len(L.lbm_last_error(None)) > 0
+    if case.startswith("iface"):
+        assert b"interface" in L.lbm_last_error(None)
+
+
+def test_refine_work_bytes(L):
+    """Two FP32 planes (recorded coarse packets, summed fine packets) of q x
+    nz x nx per interface side, two sides."""
+    out = ctypes.c_size_t(0)
+    d = lbm.make_domain((24, 8, 10))
+    for q in (19, 27):
+        assert L.lbm_refine_work_bytes(ctypes.byref(d), q, ctypes.byref(out)) == lbm.LBM_OK
+        assert out.value == 4 * q * 24 * 10 * 4
+    assert L.lbm_refine_work_bytes(ctypes.byref(d), 15, ctypes.byref(out)) == lbm.LBM_EINVAL
+    assert L.lbm_refine_work_bytes(None, 19, ctypes.byref(out)) == lbm.LBM_EINVAL
+    assert L.lbm_refine_step(None, None, None, None, 0, 1) == lbm.LBM_EINVAL
 
 
 def test_hrr_workspace_holds_two_velocity_fields(L):
