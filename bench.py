@@ -375,6 +375,118 @@ def gpu_l2(form, refs):
             "streaming": cfg["streaming"]}
 
 
+# ---------------------------------------------------------------------------
+# 2:1 refinement: a wall-refined channel (fine levels at both walls, a coarse
+# core); one coarse and two fine steps per call of lbm_refine_step
+# ---------------------------------------------------------------------------
+REFINED = "refined_channel_512x128x256_d3q19_f32"
+REFINED_L2_COPY = (64, 16, 32, 8, 100)  # coarse nx, ny, nz; fine ny; coarse steps
+
+
+def refined_cfgs(nxc=512, nyc=128, nzc=256, nyf=64, storage="f32"):
+    """Coarse core (nxc, nyc, nzc) between fine levels (2 nxc, nyf, 2 nzc) at
+    the walls: channel height nyc + nyf coarse cells, body force for a
+    centreline velocity of 0.05, tau_c = 0.51 (tau_f = 0.52, F_f = F_c / 2)."""
+    H = nyc + nyf
+    tau = 0.51
+    F = 8 * ((tau - 0.5) / 3) * 0.05 / H ** 2
+    per = ("periodic", "periodic")
+    mk = lambda name, shape, bc, t, f, y0, h: dict(name=name, shape=shape, q=19, tau=t, force=(f, 0.0, 0.0), bc=bc,
+                                                  u_bc=None, solid=None, storage=storage, closure="none",
+                                                  y0=y0, h=h, height=H)
+    return {"lo": mk("lo", (2 * nxc, nyf, 2 * nzc), per + ("noslip", "interface") + per, 0.5 + 2 * (tau - 0.5), F / 2,
+                     0.0, 0.5),
+            "c": mk("c", (nxc, nyc, nzc), per + ("interface", "interface") + per, tau, F, nyf / 2, 1.0),
+            "hi": mk("hi", (2 * nxc, nyf, 2 * nzc), per + ("interface", "noslip") + per, 0.5 + 2 * (tau - 0.5), F / 2,
+                     nyf / 2 + nyc, 0.5)}
+
+
+def refined_fields(cfg, seed):
+    from paper_2305_09910_amd import inputs
+    nx, ny, nz = cfg["shape"]
+    return inputs.channel_level(nx, ny, nz, cfg["y0"], cfg["h"], cfg["height"], 0.05, 0.05, seed=seed)
+
+
+def make_refined(cfgs):
+    from paper_2305_09910_amd import lbm
+    lats = {}
+    for k, (name, cfg) in enumerate(cfgs.items()):
+        lat = lbm.Lattice(cfg["shape"], q=19, tau=cfg["tau"], force=cfg["force"], bc=cfg["bc"], storage=cfg["storage"])
+        lat.init_equilibrium(*refined_fields(cfg, 1234 + k))
+        lats[name] = lat
+    return lats
+
+
+def time_refined(steps, warmup):
+    """Cell updates per second over all levels (coarse cells once, fine cells
+    twice per coarse step), and the share of the time spent outside the
+    levels' own step kernels (the exchange kernels and their launches)."""
+    import torch
+    from paper_2305_09910_amd import lbm
+    cfgs = refined_cfgs()
+    lats = make_refined(cfgs)
+    c, lo, hi = lats["c"], lats["lo"], lats["hi"]
+    lbm.refine_step(c, lo, hi, warmup)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record(c.stream)
+    lbm.refine_step(c, lo, hi, steps)
+    b.record(c.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = a.elapsed_time(b)
+    # the same level steps without the exchange (their states advance further; timing only)
+    a2, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a2.record(c.stream)
+    for _ in range(steps):
+        c.step(1)
+        lo.step(2)
+        hi.step(2)
+    b2.record(c.stream)
+    torch.cuda.synchronize()
+    ms_levels = a2.elapsed_time(b2)
+    ncs = [cfgs[k]["shape"][0] * cfgs[k]["shape"][1] * cfgs[k]["shape"][2] for k in ("c", "lo", "hi")]
+    updates = ncs[0] + 2 * (ncs[1] + ncs[2])
+    nb = bytes_per_cell(19, BYTES["f32"])
+    plane = cfgs["c"]["shape"][0] * cfgs["c"]["shape"][2]
+    # per side and coarse step, 5 crossing directions: record 8 B, 2 adds of 20 B, 2 fine fills of
+    # 4 x 8 B, one coarse fill of 8 B per coarse interface cell and direction
+    xbytes = 2 * 5 * plane * (8 + 2 * 20 + 2 * 32 + 8)
+    moved = updates * nb + xbytes
+    del lats, c, lo, hi
+    torch.cuda.empty_cache()
+    return {"mlups": round(updates * steps / wall / 1e6, 1), "kernel_mlups": round(updates * steps / (ms * 1e-3) / 1e6, 1),
+            "cell_updates_per_coarse_step": updates, "levels": {k: cfgs[k]["shape"] for k in ("lo", "c", "hi")},
+            "bytes_per_coarse_step": moved, "achieved_gbs": round(moved * steps / (ms * 1e-3) / 1e9, 1),
+            "roofline_frac": round(moved * steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "exchange_share": round(max(0.0, 1 - ms_levels / ms), 4), "us_per_coarse_step": round(1e3 * ms / steps, 1)}
+
+
+def refined_l2():
+    """Velocity L2 error of the refined form's copy (coarse 64x16x32, fine
+    128x8x64 at both walls, 100 coarse steps) against the oracle, per level."""
+    import oracle
+    from paper_2305_09910_amd import lbm
+    nxc, nyc, nzc, nyf, steps = REFINED_L2_COPY
+    cfgs = refined_cfgs(nxc, nyc, nzc, nyf)
+    bcs = {"periodic": oracle.BC_PERIODIC, "noslip": oracle.BC_NOSLIP, "interface": oracle.BC_INTERFACE}
+    orc = {}
+    for k, (name, cfg) in enumerate(cfgs.items()):
+        o = oracle.Sim(19, cfg["shape"], bc=tuple(bcs[b] for b in cfg["bc"]), tau=cfg["tau"], force=cfg["force"])
+        o.init_equilibrium(*refined_fields(cfg, 1234 + k))
+        orc[name] = o
+    oracle.refine_step(orc["c"], orc["lo"], orc["hi"], steps)
+    lats = make_refined(cfgs)
+    lbm.refine_step(lats["c"], lats["lo"], lats["hi"], steps)
+    out = {}
+    for name in ("lo", "c", "hi"):
+        ug = lats[name].moments()[1].cpu().numpy()
+        out[name] = float(f"{velocity_l2(ug, orc[name].moments()[1]):.3g}")
+    return {"value": max(out.values()), "per_level": out, "copy": f"coarse {nxc}x{nyc}x{nzc}, fine {2 * nxc}x{nyf}x"
+            f"{2 * nzc} at both walls", "steps": steps}
+
+
 PAPER_CONTEXT = {
     "kernel_mlups_per_node": 874, "roofline_mlups_per_node": 977, "bandwidth_gbs": 297.9, "bytes_per_cell": 304,
     "hardware": "one HAWK node, 2x AMD EPYC 7742 (128 cores), STREAM bandwidth",
@@ -449,7 +561,7 @@ def main():
     ap.add_argument("--form-steps", type=int, default=300)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB once with the library's copy kernel (counter calibration)")
-    ap.add_argument("--only-form", choices=[HEADLINE] + FORMS, default=None,
+    ap.add_argument("--only-form", choices=[HEADLINE] + FORMS + [REFINED], default=None,
                     help="time only this form for --form-steps steps (for profiling); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -473,6 +585,10 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
 
+    if args.only_form == REFINED:
+        log(f"[bench] form {REFINED}, {args.form_steps} coarse steps")
+        log(f"[bench]   {time_refined(args.form_steps, 20)}")
+        return
     if args.only_form:
         log(f"[bench] form {args.only_form}, {args.form_steps} steps")
         fr = time_lattice(form_cfg(args.only_form), args.form_steps, 50, diag_every=0)
@@ -504,13 +620,21 @@ def main():
             if key in NOTES:
                 forms[key]["note"] = NOTES[key]
             log(f"[bench]   {forms[key]}")
+        log(f"[bench] form {REFINED}, {fs} coarse steps")
+        forms[REFINED] = time_refined(fs, 20)
+        forms[REFINED]["note"] = ("2:1 refinement: fine levels at both walls, coarse core; MLUPS count every "
+                                  "level's cell updates (fine cells twice per coarse step)")
+        log(f"[bench]   {forms[REFINED]}")
 
     cpu, l2 = None, {}
     if not args.no_cpu_baseline:
         log("[bench] oracle leg: cpu baseline and velocity L2 references (oracle on host cores)")
-        cpu, refs = oracle_leg([HEADLINE] + list(forms))
+        cpu, refs = oracle_leg([HEADLINE] + [f for f in forms if f != REFINED])
         log(f"[bench]   {cpu}")
-        for key in [HEADLINE] + list(forms):
+        if REFINED in forms:
+            forms[REFINED]["velocity_l2_vs_oracle"] = refined_l2()
+            log(f"[bench]   velocity L2 {REFINED}: {forms[REFINED]['velocity_l2_vs_oracle']}")
+        for key in [HEADLINE] + [f for f in forms if f != REFINED]:
             l2[key] = gpu_l2(key, refs)
             log(f"[bench]   velocity L2 {key}: {l2[key]}")
             if key in forms:

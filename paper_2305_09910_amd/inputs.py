@@ -136,6 +136,26 @@ def porous(nx: int, ny: int, nz: int, solid_fraction: float = 0.7, rmin: float =
     return mask
 
 
+def channel_level(nx: int, ny: int, nz: int, y0: float, h: float, height: float, u_c: float = 0.05,
+                  noise: float = 0.05, seed: int = 1234):
+    """One level of a channel split into refinement levels along y: cells of
+    size h (in units of the coarsest cell) whose first row starts at y0, in a
+    channel of total height `height` with walls at 0 and `height`.
+
+    u_x = 4 u_c y (height - y) / height^2 at the cell centres y = y0 + (j + 1/2) h,
+    plus i.i.d. uniform noise in [-noise u_c, noise u_c] on every component
+    (numpy's PCG64(seed), C order (z, y, x, component)); rho = 1."""
+    y = y0 + (np.arange(ny, dtype=np.float64) + 0.5) * h
+    prof = 4.0 * u_c * y * (height - y) / (height * height)
+    shape = (nz, ny, nx)
+    u = np.zeros((3,) + shape)
+    u[0] = prof[None, :, None]
+    if noise > 0.0:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        u += np.moveaxis(rng.uniform(-noise * u_c, noise * u_c, size=shape + (3,)), -1, 0)
+    return np.ones(shape), u
+
+
 def uniform_flow(nx: int, ny: int, nz: int, u=(0.04, 0.0, 0.0), rho: float = 1.0):
     shape = (nz, ny, nx)
     uu = np.zeros((3,) + shape)
