@@ -274,6 +274,16 @@ int lbm_set_closure_weights(lbm_ctx *ctx, const float *params, size_t n);
  * (host); resets the counter.  Synchronises.  LBM_EINVAL for NULL. */
 int lbm_closure_fallbacks(lbm_ctx *ctx, int64_t *count);
 
+/* The learned closure's six inputs of every cell, from the current state,
+ * as the fused closure computes them before its network (the subgrid model
+ * of the Section 5.1 LES channel): tr P, |dev P|, cbrt det dev P of
+ * P = P_c / rho, rho - 1, tau_s - tau (Smagorinsky with cs_smag) and tau,
+ * where P_c is the non-equilibrium momentum flux with its forcing
+ * correction.  x_dev [n][6] FP32 (device, caller owned); solid cells get
+ * NaN.  Works with any closure setting (the features do not depend on it).
+ * Asynchronous.  LBM_EINVAL for NULL. */
+int lbm_closure_features(lbm_ctx *ctx, float *x_dev);
+
 /* ------------------------------------------------------------------------ */
 /* Training-data and training kernels of the learned closure (the subgrid   */
 /* stresses of the Section 5.1 LES channel).  All pointers are device       */

@@ -9,7 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_et.hip", "lbm_sparse.hip", "lbm_closure.hip", "lbm_refine.hip", "lbm_api.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_et.hip", "lbm_sparse.hip", "lbm_closure.hip", "lbm_refine.hip", "lbm_features.hip", "lbm_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

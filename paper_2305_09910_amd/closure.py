@@ -7,8 +7,11 @@ only holds device memory and selects minibatches):
    same lattice velocity, nu_fine = factor * nu_coarse, F_fine = F / factor)
    is spun up, then snapshots are taken.
 2. Each snapshot: density and velocity (lbm_moments) -> 4^3 box filter
-   (lbm_box_filter4) -> per coarse cell six flux invariants and the target
-   relaxation-time correction (lbm_closure_dataset).
+   (lbm_box_filter4) -> per coarse cell the target relaxation-time
+   correction (lbm_closure_dataset), and the six flux invariants either of
+   the filtered strain (lbm_closure_dataset, the default) or of a coarse
+   lattice run up to the snapshot from an earlier filtered state
+   (lbm_closure_features: the inputs the network meets inside the lattice).
 3. The MLP 6 -> 32 -> 32 -> 1 is trained with the library's forward /
    backward (bfloat16 matrix cores) and Adam kernels.
 4. Evaluation a priori (mean-squared error of the predicted correction on a
@@ -48,6 +51,10 @@ class ClosureConfig:
     batch: int = 65536
     lr: float = 2e-3
     eval_coarse_steps: int = 200     # a-posteriori horizon in coarse steps
+    features: str = "filtered"       # "lattice": inputs from a coarse lattice's own populations; "filtered":
+                                     # inputs from the filtered strain (P = -(2/3)(tau + dtau*) S)
+    lead: int = 25                   # "lattice": coarse steps from the earlier filtered state to the snapshot
+    target_scale: float = 1.0        # training targets alpha * dtau* (a-posteriori calibration of the dissipation)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -99,22 +106,53 @@ def dataset(cfg: ClosureConfig, filt):
     return lbm.closure_dataset(filt, (1, 0, 1), cfg.tau_c, cfg.cs)
 
 
+def coarse_features(cfg: ClosureConfig, filt, steps):
+    """The closure inputs a coarse lattice produces from its own populations
+    (lbm_closure_features), `steps` coarse steps after starting from the
+    filtered state `filt` with the Smagorinsky closure: the inputs the
+    network meets when it runs inside the lattice, whose non-equilibrium
+    flux carries the lattice's own acoustic and truncation parts that the
+    filtered strain lacks."""
+    c = lbm.Lattice(cfg.coarse, q=19, tau=cfg.tau_c, force=(cfg.force_c, 0, 0), bc=WALLS_Y, closure="smagorinsky",
+                    cs=cfg.cs)
+    c.init_equilibrium(filt[0].double(), filt[1:4].double())
+    c.step(steps)
+    x = c.closure_features()
+    c.close()
+    return x
+
+
 def generate(cfg: ClosureConfig, log=print):
     """Fine run -> (training features, targets), held-out (x, t), and the
-    filtered field and fine lattice at the held-out time (for a-posteriori)."""
+    filtered field and fine lattice at the held-out time (for a-posteriori).
+
+    Targets come from the filtered fine field at each snapshot.  Features:
+    with cfg.features == "filtered", from the same filtered field
+    (lbm_closure_dataset); with "lattice", from a coarse lattice run
+    cfg.lead coarse steps from the filtered state cfg.lead coarse steps
+    earlier, so that it reaches the snapshot's time (coarse_features)."""
     torch = _torch()
+    if cfg.features not in ("lattice", "filtered"):
+        raise ValueError(f"unknown feature source {cfg.features!r}")
+    lead = cfg.lead * cfg.factor if cfg.features == "lattice" else 0
+    if lead > cfg.spinup or lead > cfg.every:
+        raise ValueError("the lead of the lattice features must fit in the spin-up and the snapshot spacing")
     lat = fine_lattice(cfg)
-    lat.step(cfg.spinup)
+    lat.step(cfg.spinup - lead)
     xs, ts = [], []
-    for k in range(cfg.snapshots):
-        x, t = dataset(cfg, filtered(lat))
+    for k in range(cfg.snapshots + 1):
+        early = filtered(lat) if lead else None
+        lat.step(lead)
+        filt = filtered(lat)
+        x, t = dataset(cfg, filt)
+        if lead:
+            x = coarse_features(cfg, early, cfg.lead)
+        if k == cfg.snapshots:
+            return torch.cat(xs), torch.cat(ts), x, t, filt, lat
         xs.append(x)
-        ts.append(t)
+        ts.append(cfg.target_scale * t)
         log(f"[closure] snapshot {k}: mean target {float(t.mean()):.3e}, nonzero {float((t > 0).float().mean()):.2f}")
-        lat.step(cfg.every)
-    filt = filtered(lat)
-    xh, th = dataset(cfg, filt)
-    return torch.cat(xs), torch.cat(ts), xh, th, filt, lat
+        lat.step(cfg.every - lead)
 
 
 def init_params(x, t, seed=0, margin=0.25):
@@ -225,12 +263,18 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval-coarse-steps", type=int, default=500)
     ap.add_argument("--seed", type=int, default=1234, help="seed of the start state and of minibatch sampling")
+    ap.add_argument("--features", choices=["lattice", "filtered"], default="filtered",
+                    help="training inputs from a coarse lattice's populations or from the filtered strain")
+    ap.add_argument("--lead", type=int, default=25, help="coarse steps of the lattice run behind each snapshot")
+    ap.add_argument("--target-scale", type=float, default=1.0,
+                    help="train on target_scale * dtau* (a-posteriori calibration of the dissipation)")
     ap.add_argument("--out", default=None, help="write the JSON result here")
     a = ap.parse_args(argv)
     cfg = ClosureConfig(coarse=tuple(a.coarse), tau_c=a.tau_c, noise=a.noise, vortical_rms=a.vortical_rms,
                         vortical_wavelength=a.vortical_wavelength, spinup=a.spinup,
                         snapshots=a.snapshots, every=a.every, train_steps=a.train_steps, batch=a.batch, lr=a.lr,
-                        eval_coarse_steps=a.eval_coarse_steps, seed=a.seed)
+                        eval_coarse_steps=a.eval_coarse_steps, seed=a.seed, features=a.features, lead=a.lead,
+                        target_scale=a.target_scale)
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -240,7 +284,7 @@ def main(argv=None):
     res["config"] = {k: getattr(cfg, k) for k in ("coarse", "factor", "tau_c", "u_c", "re_tau", "noise",
                                                    "vortical_rms", "vortical_wavelength", "seed", "cs",
                                                    "spinup", "snapshots", "every", "train_steps", "batch", "lr",
-                                                   "eval_coarse_steps")}
+                                                   "eval_coarse_steps", "features", "lead", "target_scale")}
     res["config"]["fine"] = cfg.fine
     line = json.dumps(res)
     print(line, flush=True)

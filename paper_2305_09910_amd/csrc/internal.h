@@ -122,6 +122,8 @@ hipError_t launch_refine_fill_coarse(const LatticeArgs &c, int q, int st, int yc
 hipError_t launch_build_mlp_table(const float *params, uint32_t *table, hipStream_t s);
 
 // closure training path (lbm_closure.hip)
+hipError_t launch_closure_features(const LatticeArgs &a, const SparseArgs &sp, int q, int st, int odd, float *x,
+                                   hipStream_t s);
 hipError_t launch_box_filter4(int nx, int ny, int nz, const float *rho, const float *u, float *out, hipStream_t s);
 hipError_t launch_closure_dataset(int cx, int cy, int cz, const int *per, const float *filt, float tau, float cs,
                                   float *x, float *t, hipStream_t s);

@@ -539,6 +539,15 @@ int lbm_set_closure_weights(lbm_ctx *c, const float *params, size_t n)
     return LBM_OK;
 }
 
+int lbm_closure_features(lbm_ctx *c, float *x_dev)
+{
+    if (!c) return fail(nullptr, LBM_EINVAL, "context is NULL");
+    if (!x_dev) return fail(c, LBM_EINVAL, "closure_features: x is NULL");
+    HIPCHECK(c, launch_closure_features(c->a, c->sp, c->q, c->st, (int)(c->time & 1), x_dev, c->stream),
+             "closure_features");
+    return LBM_OK;
+}
+
 int lbm_closure_fallbacks(lbm_ctx *c, int64_t *count)
 {
     if (!c || !count) return fail(c, LBM_EINVAL, "context/count is NULL");

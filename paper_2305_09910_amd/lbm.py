@@ -33,7 +33,7 @@ EXPORTED = [
     "lbm_moments", "lbm_totals", "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
     "lbm_set_closure_weights", "lbm_closure_fallbacks", "lbm_box_filter4", "lbm_closure_dataset",
     "lbm_mlp_forward", "lbm_mlp_work_bytes", "lbm_mlp_loss_grad", "lbm_mlp_loss_grad_noalloc", "lbm_mlp_adam",
-    "lbm_stream_copy", "lbm_refine_work_bytes", "lbm_refine_step",
+    "lbm_stream_copy", "lbm_refine_work_bytes", "lbm_refine_step", "lbm_closure_features",
 ]
 
 
@@ -100,6 +100,7 @@ def lib():
             "lbm_stream_copy": (ctypes.c_int, [P, P, SZ, P]),
             "lbm_refine_work_bytes": (ctypes.c_int, [DP, ctypes.c_int, ctypes.POINTER(SZ)]),
             "lbm_refine_step": (ctypes.c_int, [P, P, P, P, SZ, I64]),
+            "lbm_closure_features": (ctypes.c_int, [P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -300,6 +301,14 @@ class Lattice:
     def set_closure_weights(self, params: np.ndarray):
         p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
         self._ck(lib().lbm_set_closure_weights(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size))
+
+    def closure_features(self):
+        """The closure's six inputs of every cell from the current state, as
+        the fused closure computes them: [n, 6] FP32 (solid cells NaN)."""
+        torch = _torch()
+        x = torch.empty((self.n, 6), dtype=torch.float32, device=self.device)
+        self._ck(lib().lbm_closure_features(self._h, x.data_ptr()))
+        return x
 
     def closure_fallbacks(self) -> int:
         c = ctypes.c_int64(0)

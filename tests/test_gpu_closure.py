@@ -366,3 +366,45 @@ def test_fused_mlp_fallback_to_smagorinsky():
     assert rel < 1e-6
     b = o.get_pdfs()
     assert float(np.max(np.abs(g.get_pdfs().cpu().numpy() - b) / np.abs(b))) < 1e-5
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_closure_features_of_a_lattice_match_oracle(q):
+    """lbm_closure_features against the oracle's flux and invariants of the
+    oracle's own state, cell by cell: the same seeded non-equilibrium start,
+    walls, a force, solid cells and the Smagorinsky closure on both sides,
+    after an odd and an even number of steps (both storage parities).  FP32
+    against FP64: 2e-5 of each feature's largest magnitude (2e-3 for the
+    cube root of det dev P, whose slope is unbounded at 0); solid cells are
+    NaN."""
+    lbm = _lbm()
+    shape = (13, 10, 6)
+    tau, cs, F = 0.56, 0.1, (3e-5, -1e-5, 0.0)
+    solid = np.zeros(shape[::-1], np.uint8)
+    solid[2:4, 3:6, 4:7] = 1
+    bc = ("periodic", "periodic", "noslip", "noslip", "periodic", "periodic")
+    lat = lbm.Lattice(shape, q=q, tau=tau, force=F, bc=bc, solid=solid, closure="smagorinsky", cs=cs)
+    o = oracle.Sim(q, shape, bc=(oracle.BC_PERIODIC,) * 2 + (oracle.BC_NOSLIP,) * 2 + (oracle.BC_PERIODIC,) * 2,
+                   tau=tau, force=F, solid=solid, closure=oracle.CL_SMAG, cs=cs)
+    c, w, _ = oracle.velocity_set(q)
+    rng = np.random.default_rng(31)
+    f = w[:, None, None, None] * (1 + 0.05 * rng.standard_normal((q,) + shape[::-1]))
+    lat.set_pdfs(f)
+    o.set_pdfs(f)
+    fl = solid == 0
+    for nsteps in (3, 2):
+        lat.step(nsteps)
+        o.step(nsteps)
+        x = lat.closure_features().cpu().numpy().reshape(shape[2], shape[1], shape[0], 6)
+        fo = o.get_pdfs()
+        ref = np.zeros(x.shape)
+        for z, y, xx in zip(*np.nonzero(fl)):
+            cell = fo[:, z, y, xx]
+            rho = cell.sum()
+            ref[z, y, xx] = oracle.features(oracle.noneq_flux(q, cell, F) / rho, rho, tau, cs)
+        assert np.isnan(x[~fl]).all()
+        for k in range(6):
+            scale = np.abs(ref[fl][:, k]).max()
+            err = np.abs(x[fl][:, k] - ref[fl][:, k]).max()
+            print(f"closure features q={q} t={lat.time} feature {k}: max err {err:.2e} of scale {scale:.2e}")
+            assert err <= (2e-3 if k == 2 else 2e-5) * scale
