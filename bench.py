@@ -622,6 +622,7 @@ def main():
             log(f"[bench]   {forms[key]}")
         log(f"[bench] form {REFINED}, {fs} coarse steps")
         forms[REFINED] = time_refined(fs, 20)
+        forms[REFINED]["frac_of_copy"] = round(forms[REFINED]["achieved_gbs"] / bs, 4) if bs else None
         forms[REFINED]["note"] = ("2:1 refinement: fine levels at both walls, coarse core; MLUPS count every "
                                   "level's cell updates (fine cells twice per coarse step)")
         log(f"[bench]   {forms[REFINED]}")
