@@ -10,6 +10,11 @@ namespace lbm {
 enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 enum { CL_NONE = 0, CL_SMAG = 1, CL_MLP = 2 };
 enum { COLL_TRT = 0, COLL_MRT = 1, COLL_HRR = 2 };
+
+// launch_step's `odd` argument: bit 0 the step parity; SC_SOLID_ODD asks the
+// masked AA kernel to rewrite solid cells' own slots on odd steps (whole
+// cache lines along solid surfaces; worth it when solids are sparse)
+constexpr int SC_SOLID_ODD = 2;
 enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
 
 // Bit 31 of a cell's mask word marks the cell itself as solid; bit i
@@ -85,6 +90,7 @@ Launch lattice_launch(const LatticeArgs &a);
 
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, uint32_t *mask, hipStream_t s);
+// odd: bit 0 the step parity, optionally | SC_SOLID_ODD
 hipError_t launch_step(const LatticeArgs &a, const HrrArgs &h, int q, int st, int cl, int coll, int odd, hipStream_t s);
 // Esoteric Twist step (lbm_et.hip)
 hipError_t launch_step_et(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);

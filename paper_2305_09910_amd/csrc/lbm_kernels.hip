@@ -36,11 +36,14 @@ namespace lbm {
 // ---------------------------------------------------------------------------
 // the fused stream-collide kernel
 // ---------------------------------------------------------------------------
+// flags: bit 0 the step parity (1: odd step); bit 1 (SC_SOLID_ODD): on the
+// odd step solid lanes rewrite their own slots unchanged (see below)
 template <int Q, int ST, int CL, bool MASK, int COLL>
 __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES)
-    k_stream_collide(LatticeArgs a, int odd, [[maybe_unused]] HrrArgs h)
+    k_stream_collide(LatticeArgs a, int flags, [[maybe_unused]] HrrArgs h)
 {
     using S = Store<ST>;
+    const int odd = flags & 1;
     constexpr bool kUnified =
         LBM_UNIFIED == 1 || (LBM_UNIFIED == 2 && (MASK || ST == ST_F32) && CL != CL_MLP);
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -67,8 +70,14 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES)
     // free, and every cache line the wavefront writes is then written whole;
     // lanes that skip would leave holes in the lines along sphere surfaces,
     // and partially written lines cost ~20% of the even step's time on the
-    // 384^3 obstacle flow.  On the odd step the addresses of a solid lane
-    // belong to its neighbours, so it leaves at once.
+    // 384^3 obstacle flow.  On the odd step no fluid cell reads or writes a
+    // solid cell's slots either (links into a solid are cut, and cut links
+    // use the fluid cell's own slots), so with SC_SOLID_ODD a solid lane
+    // rewrites its own slots unchanged on the odd step too, filling the holes
+    // that solid cells leave in the lines its row's neighbours write.  That
+    // costs the solid cells' bytes: it pays on sparse solids (384^3 obstacle
+    // flow, 10% solid: odd step -2.9%) and not on dense ones (70%-solid porous
+    // medium: +41%), so the host sets the flag by the solid fraction.
     constexpr bool kKeepSolid = MASK && kUnified && CL != CL_MLP;
     bool keep = false;
     const Geom g = make_geom(a, active ? x : 0, active ? y : 0, z);
@@ -77,7 +86,19 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES)
         m = active ? a.mask[cidx(a, g)] : 0u;
         if (m & SELF_SOLID) {
             if constexpr (kKeepSolid) {
-                if (odd) return;
+                if (odd) {
+                    if (flags & SC_SOLID_ODD) {
+                        typename S::T *A = (typename S::T *)a.pdf;
+                        float v[Q];
+#pragma unroll
+                        for (int i = 0; i < Q; ++i) v[i] = S::ld(A + pidx<Q>(a, i, g.row, g.x));
+                        // (+ 0: a store the compiler cannot drop as a no-op;
+                        // at most turns -0 into +0 in a slot no one reads)
+#pragma unroll
+                        for (int i = 0; i < Q; ++i) S::st(A + pidx<Q>(a, i, g.row, g.x), v[i] + 0.0f);
+                    }
+                    return;
+                }
                 keep = true;
             } else {
                 if constexpr (CL != CL_MLP) return;
@@ -515,7 +536,7 @@ static bool even_pair16(const LatticeArgs &a, int cl, int coll, hipStream_t s)
 template <int Q, int ST>
 static hipError_t step_q_st(const LatticeArgs &a, const HrrArgs &h, int cl, int coll, int odd, hipStream_t s)
 {
-    if (!odd && even_pair16<Q, ST>(a, cl, coll, s)) return hipGetLastError();
+    if (!(odd & 1) && even_pair16<Q, ST>(a, cl, coll, s)) return hipGetLastError();
     const Launch L = lattice_launch(a);
     const bool mk = a.mask != nullptr;
     if (cl == CL_MLP) {  // the learned closure runs with the TRT collision
