@@ -650,31 +650,38 @@ __device__ inline void hrr_collide(const LatticeArgs &a, float sigma, const floa
     const float uF = ux * F0 + uy * F1 + uz * F2;
     const float base = drho - 1.5f * R * usq;
     const float trp = (pxx + pyy + pzz) * (1.f / 3.f);
-    for_dirs<0, Q>([&](auto I) {
+    // Pairs (i, opposite(i)): the equilibrium's quadratic part, the
+    // second-order term and the forcing's -uF and cu cF parts are even in c
+    // (E), the linear parts and the third-order term odd (O), so
+    // f*_i = E + O and f*_opp(i) = E - O.
+    float even_sum = 0.f;
+    for_dirs<1, Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
-        constexpr int cx = cdir(i, 0), cy = cdir(i, 1), cz = cdir(i, 2);
-        constexpr float w = (float)wgt<Q>(i);
-        const float cu = cx * ux + cy * uy + cz * uz;
-        const float cF = cx * F0 + cy * F1 + cz * F2;
-        const float deq = w * (base + R * (3.f * cu + 4.5f * cu * cu));
-        const float h2 = (float)(cx * cx) * pxx + (float)(cy * cy) * pyy + (float)(cz * cz) * pzz +
-                         2.f * ((float)(cx * cy) * pxy + (float)(cx * cz) * pxz + (float)(cy * cz) * pyz) - trp;
-        float t3 = 0.f;
-        for_dirs<0, 6>([&](auto K) {
-            constexpr int k = decltype(K)::value;
-            constexpr float tv = (float)t3val(i, k);
-            if constexpr (tv != 0.f) t3 += tv * Bk[k];
-        });
-        const float S = w * (3.f * (cF - uF) + 9.f * cu * cF);
-        d[i] = deq + w * (k1 * 4.5f * h2 + t3) + 0.5f * S;
+        if constexpr (i & 1) {
+            constexpr int cx = cdir(i, 0), cy = cdir(i, 1), cz = cdir(i, 2);
+            constexpr float w = (float)wgt<Q>(i);
+            const float cu = cx * ux + cy * uy + cz * uz;
+            const float cF = cx * F0 + cy * F1 + cz * F2;
+            const float h2 = (float)(cx * cx) * pxx + (float)(cy * cy) * pyy + (float)(cz * cz) * pzz +
+                             2.f * ((float)(cx * cy) * pxy + (float)(cx * cz) * pxz + (float)(cy * cz) * pyz) - trp;
+            float t3 = 0.f;
+            for_dirs<0, 6>([&](auto K) {
+                constexpr int k = decltype(K)::value;
+                constexpr float tv = (float)t3val(i, k);
+                if constexpr (tv != 0.f) t3 += tv * Bk[k];
+            });
+            const float E = w * (base + 4.5f * R * cu * cu + k1 * 4.5f * h2 + 0.5f * (9.f * cu * cF - 3.f * uF));
+            const float O = w * (3.f * R * cu + t3 + 1.5f * cF);
+            d[i] = E + O;
+            d[opp(i)] = E - O;
+            even_sum += E;
+        }
     });
     // The update keeps the cell's mass exactly (sum f* = rho); the rest
-    // population takes what the moving ones leave, so FP32 rounding of the
-    // moving ones cannot drift the total mass.
-    float moving = 0.f;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) moving += d[i];
-    d[0] = drho - moving;
+    // population takes what the moving ones leave (their sum is twice the
+    // even parts' sum), so FP32 rounding of the moving ones cannot drift the
+    // total mass.
+    d[0] = drho - 2.f * even_sum;
 }
 
 // Canonical read for the state kernels, any scheme.  With sparse addressing
