@@ -384,7 +384,9 @@ int lbm_refine_work_bytes(const lbm_domain *coarse, int stencil, size_t *bytes);
  * work_dev: device buffer of at least lbm_refine_work_bytes (caller owned,
  * 4-byte aligned).  Asynchronous, on the shared stream.  LBM_EINVAL when
  * the lattices do not form a refinement as stated above, for a NULL or
- * small work buffer or n < 0; LBM_EDEVICE when a launch fails. */
+ * small work buffer or n < 0 (checked before any work is enqueued);
+ * LBM_EDEVICE when a launch fails, which leaves the lattices part way
+ * through a coarse step (restore them from a checkpoint). */
 int lbm_refine_step(lbm_ctx *coarse, lbm_ctx *fine_lo, lbm_ctx *fine_hi, void *work_dev, size_t work_bytes,
                     int64_t n);
 

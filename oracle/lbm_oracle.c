@@ -1179,7 +1179,8 @@ static void refine_fill_coarse(orc_sim *c, int yc, int dy, const double *acc)
 }
 
 /* Advance the coarse lattice n steps and each fine lattice (nullable)      */
-/* 2n steps.  Returns -1 if the lattices do not form a refinement.          */
+/* 2n steps.  Returns -1 if the lattices do not form a refinement (or the   */
+/* exchange buffer cannot be allocated).                                    */
 int orc_refine_step(orc_sim *c, orc_sim *fine_lo, orc_sim *fine_hi, int64_t n)
 {
     if (refine_pair_ok(c, fine_lo, 0) || refine_pair_ok(c, fine_hi, 1)) return -1;
@@ -1187,6 +1188,7 @@ int orc_refine_step(orc_sim *c, orc_sim *fine_lo, orc_sim *fine_hi, int64_t n)
     orc_sim *fl[2] = {fine_lo, fine_hi};
     int64_t plane = (int64_t)c->nx * c->nz;
     double *buf = (double *)calloc((size_t)(4 * c->q * plane), sizeof(double));
+    if (!buf) return -1;
     ensure_lattices(c);
     for (int k = 0; k < 2; ++k)
         if (fl[k]) ensure_lattices(fl[k]);
