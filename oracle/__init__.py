@@ -86,6 +86,8 @@ def lib():
         L.orc_fd_gradient.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         L.orc_refine_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        L.orc_refine_tree_step.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int64]
         L.orc_moments.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_totals.argtypes = [ctypes.c_void_p, _D, _D]
         L.orc_probe.argtypes = [ctypes.c_void_p, _D, _D, ctypes.c_int, ctypes.c_int64, _I64, _D]
@@ -248,6 +250,19 @@ def closure_dataset(filt, periodic, tau, cs=0.1, eps=1e-30):
     lib().orc_closure_dataset(cx, cy, cz, per.ctypes.data_as(_I), _d(filt), float(tau), float(cs), float(eps),
                               _d(x), _d(t))
     return x, t
+
+
+def refine_tree_step(nodes, n=1):
+    """Advance a hierarchy of 2:1 levels: nodes is a list of (Sim, lo, hi)
+    with lo / hi the indices of the finer Sims below / above (None for
+    none), children after their parent, node 0 the coarsest; node 0 takes n
+    steps, a node at depth d 2^d n steps."""
+    k = len(nodes)
+    sims = (ctypes.c_void_p * k)(*[nd[0]._h.value for nd in nodes])
+    lo = (ctypes.c_int * k)(*[-1 if nd[1] is None else int(nd[1]) for nd in nodes])
+    hi = (ctypes.c_int * k)(*[-1 if nd[2] is None else int(nd[2]) for nd in nodes])
+    if lib().orc_refine_tree_step(sims, lo, hi, k, int(n)) != 0:
+        raise ValueError("these lattices do not form a 2:1 refinement tree")
 
 
 def refine_step(coarse, fine_lo=None, fine_hi=None, n=1):

@@ -1178,42 +1178,117 @@ static void refine_fill_coarse(orc_sim *c, int yc, int dy, const double *acc)
     }
 }
 
-/* Advance the coarse lattice n steps and each fine lattice (nullable)      */
+/* A hierarchy of levels (the paper's block forest refines 2:1 level by      */
+/* level, Section 3; the LAGOON runs use ten levels, Section 5.2): node k is  */
+/* lattice sims[k] with finer lattices lo[k] below and hi[k] above it (node   */
+/* indices, -1 for none), children after their parent, node 0 the coarsest.  */
+/* Advancing a node one step: its lattice takes one step; for each child, the */
+/* packets crossing into it are recorded and, twice, the child advances one   */
+/* step (recursively, its own children included), its packets are added and  */
+/* its interface row takes the recorded packets; then the node's interface    */
+/* rows take the sums.  Each pair of levels exchanges as stated above, and    */
+/* sum over levels of M_level / 8^level is conserved exactly.                 */
+typedef struct {
+    orc_sim **sims;
+    const int *lo, *hi;
+    double **buf; /* per node: [2 sides][cout, acc][q][nz][nx] or NULL */
+} refine_tree;
+
+static void refine_advance(const refine_tree *T, int k)
+{
+    orc_sim *c = T->sims[k];
+    int child[2] = {T->lo[k], T->hi[k]};
+    int64_t plane = (int64_t)c->nx * c->nz;
+    orc_step(c, 1);
+    for (int side = 0; side < 2; ++side) {
+        if (child[side] < 0) continue;
+        orc_sim *f = T->sims[child[side]];
+        int dy = side ? 1 : -1, yc = side ? c->ny - 1 : 0, yf = side ? 0 : f->ny - 1;
+        double *cout = T->buf[k] + (int64_t)(2 * side) * c->q * plane, *acc = cout + (int64_t)c->q * plane;
+        refine_record_coarse(c, yc, dy, cout);
+        for (int sub = 0; sub < 2; ++sub) {
+            refine_advance(T, child[side]);
+            refine_add_fine(f, c, yf, dy, acc, sub == 0);
+            refine_fill_fine(f, c, yf, dy, cout);
+        }
+    }
+    for (int side = 0; side < 2; ++side) {
+        if (child[side] < 0) continue;
+        int dy = side ? 1 : -1, yc = side ? c->ny - 1 : 0;
+        refine_fill_coarse(c, yc, dy, T->buf[k] + (int64_t)(2 * side + 1) * c->q * plane);
+    }
+}
+
+/* Advance the hierarchy n steps of node 0 (a node at depth d takes 2^d n   */
+/* steps).  Returns -1 if the nodes do not form a refinement tree: a child   */
+/* index not after its parent, a node with two parents or none (except node */
+/* 0), an interface face without a child or a child without an interface    */
+/* face, or a parent/child pair that does not fit (refine_pair_ok); or if a */
+/* buffer cannot be allocated.                                              */
+int orc_refine_tree_step(orc_sim **sims, const int *lo, const int *hi, int count, int64_t n)
+{
+    if (count < 1 || count > 4096) return -1;
+    int *parents = (int *)calloc((size_t)count, sizeof(int));
+    int *up = (int *)calloc((size_t)count, sizeof(int)); /* face index toward the parent, 0 for none */
+    double **buf = (double **)calloc((size_t)count, sizeof(double *));
+    int bad = !parents || !up || !buf;
+    for (int k = 0; k < count && !bad; ++k) {
+        int child[2] = {lo[k], hi[k]};
+        if (!sims[k]) bad = 1;
+        for (int side = 0; side < 2 && !bad; ++side) {
+            if (child[side] < 0) continue;
+            if (child[side] <= k || child[side] >= count || !sims[child[side]]) { bad = 1; break; }
+            parents[child[side]]++;
+            up[child[side]] = side ? 2 : 3; /* a lower child meets its parent with its +y face */
+            if (refine_pair_ok(sims[k], sims[child[side]], side)) bad = 1;
+        }
+    }
+    for (int k = 1; k < count && !bad; ++k)
+        if (parents[k] != 1) bad = 1;
+    /* a y face is an interface exactly where it leads to a child or faces the parent */
+    for (int k = 0; k < count && !bad; ++k) {
+        int child[2] = {lo[k], hi[k]};
+        for (int side = 0; side < 2 && !bad; ++side) {
+            int face = side ? 3 : 2, has = child[side] >= 0, toward = up[k] == face;
+            if (has && toward) bad = 1;
+            else if ((sims[k]->bc[face] == BC_INTERFACE) != (has || toward)) bad = 1;
+        }
+    }
+    for (int k = 0; k < count && !bad; ++k) {
+        ensure_lattices(sims[k]);
+        if (lo[k] >= 0 || hi[k] >= 0) {
+            buf[k] = (double *)calloc((size_t)(4 * sims[k]->q * (int64_t)sims[k]->nx * sims[k]->nz), sizeof(double));
+            if (!buf[k]) bad = 1;
+        }
+    }
+    if (!bad) {
+        refine_tree T = {sims, lo, hi, buf};
+        for (int64_t t = 0; t < n; ++t) refine_advance(&T, 0);
+    }
+    if (buf)
+        for (int k = 0; k < count; ++k) free(buf[k]);
+    free(buf);
+    free(up);
+    free(parents);
+    return bad ? -1 : 0;
+}
+
+/* Two levels: the coarse lattice n steps and each fine lattice (nullable)  */
 /* 2n steps.  Returns -1 if the lattices do not form a refinement (or the   */
 /* exchange buffer cannot be allocated).                                    */
 int orc_refine_step(orc_sim *c, orc_sim *fine_lo, orc_sim *fine_hi, int64_t n)
 {
-    if (refine_pair_ok(c, fine_lo, 0) || refine_pair_ok(c, fine_hi, 1)) return -1;
-    if ((c->bc[2] == BC_INTERFACE) != (fine_lo != 0) || (c->bc[3] == BC_INTERFACE) != (fine_hi != 0)) return -1;
-    orc_sim *fl[2] = {fine_lo, fine_hi};
-    int64_t plane = (int64_t)c->nx * c->nz;
-    double *buf = (double *)calloc((size_t)(4 * c->q * plane), sizeof(double));
-    if (!buf) return -1;
-    ensure_lattices(c);
-    for (int k = 0; k < 2; ++k)
-        if (fl[k]) ensure_lattices(fl[k]);
-    for (int64_t t = 0; t < n; ++t) {
-        orc_step(c, 1);
-        for (int k = 0; k < 2; ++k) {
-            orc_sim *f = fl[k];
-            if (!f) continue;
-            int dy = k ? 1 : -1, yc = k ? c->ny - 1 : 0, yf = k ? 0 : f->ny - 1;
-            double *cout = buf + (int64_t)(2 * k) * c->q * plane, *acc = cout + (int64_t)c->q * plane;
-            refine_record_coarse(c, yc, dy, cout);
-            for (int sub = 0; sub < 2; ++sub) {
-                orc_step(f, 1);
-                refine_add_fine(f, c, yf, dy, acc, sub == 0);
-                refine_fill_fine(f, c, yf, dy, cout);
-            }
-        }
-        for (int k = 0; k < 2; ++k) {
-            if (!fl[k]) continue;
-            int dy = k ? 1 : -1, yc = k ? c->ny - 1 : 0;
-            refine_fill_coarse(c, yc, dy, buf + (int64_t)(2 * k + 1) * c->q * plane);
-        }
+    orc_sim *sims[3] = {c, 0, 0};
+    int lo[3] = {-1, -1, -1}, hi[3] = {-1, -1, -1}, count = 1;
+    if (fine_lo) {
+        sims[count] = fine_lo;
+        lo[0] = count++;
     }
-    free(buf);
-    return 0;
+    if (fine_hi) {
+        sims[count] = fine_hi;
+        hi[0] = count++;
+    }
+    return orc_refine_tree_step(sims, lo, hi, count, n);
 }
 
 /* Density and velocity u = (j + F/2)/rho of the canonical state; u [3][n]. */

@@ -287,3 +287,166 @@ def test_refine_rejects_lattices_that_do_not_fit(case):
             oracle.refine_step(c, None, None)
         else:
             oracle.refine_step(c, None, f)
+
+
+# --------------------------------------------------------------------------
+# hierarchies of levels (orc_refine_tree_step)
+# --------------------------------------------------------------------------
+def stack(nxc, nyc, nzc, nym, nyf, tau, F=(0.0, 0.0, 0.0), q=19, outer=(NS, NS), u_bc=None):
+    """Five lattices, finest at both walls: fine (4x) / medium (2x) / coarse /
+    medium / fine along y; tau and F scaled per level. Returns the node list
+    (Sim, lower child, upper child) with the coarse lattice first."""
+    ub = np.zeros((6, 3)) if u_bc is None else u_bc
+    F = np.asarray(F, float)
+    tm, tf = 0.5 + 2 * (tau - 0.5), 0.5 + 4 * (tau - 0.5)
+    c = oracle.Sim(q, (nxc, nyc, nzc), bc=(P, P, I, I, P, P), tau=tau, force=tuple(F), u_bc=ub)
+    ml = oracle.Sim(q, (2 * nxc, nym, 2 * nzc), bc=(P, P, I, I, P, P), tau=tm, force=tuple(F / 2), u_bc=ub)
+    mh = oracle.Sim(q, (2 * nxc, nym, 2 * nzc), bc=(P, P, I, I, P, P), tau=tm, force=tuple(F / 2), u_bc=ub)
+    fl = oracle.Sim(q, (4 * nxc, nyf, 4 * nzc), bc=(P, P, outer[0], I, P, P), tau=tf, force=tuple(F / 4), u_bc=ub)
+    fh = oracle.Sim(q, (4 * nxc, nyf, 4 * nzc), bc=(P, P, I, outer[1], P, P), tau=tf, force=tuple(F / 4), u_bc=ub)
+    return [(c, 1, 2), (ml, 3, None), (mh, None, 4), (fl, None, None), (fh, None, None)]
+
+
+DEPTH = [0, 1, 1, 2, 2]
+
+
+def tree_mass(nodes):
+    return sum(nd[0].totals()[0] / 8.0 ** d for nd, d in zip(nodes, DEPTH))
+
+
+def test_refine_tree_conserves_mass_exactly():
+    """Random non-equilibrium states on all five lattices, walls outside (a
+    moving lid on top): sum over levels of M / 8^depth stays constant."""
+    ub = np.zeros((6, 3))
+    ub[3] = (0.03, 0, -0.01)
+    nodes = stack(3, 4, 2, 4, 4, 0.6, (1e-5, 0, 0), outer=(NS, V), u_bc=ub)
+    for k, nd in enumerate(nodes):
+        random_state(nd[0], 40 + k)
+    m0 = tree_mass(nodes)
+    for _ in range(3):
+        oracle.refine_tree_step(nodes, 4)
+        assert abs(tree_mass(nodes) - m0) <= 2e-14 * m0
+
+
+def test_refine_tree_uniform_moving_state_is_a_fixed_point():
+    u0 = np.array([0.03, 0.0, 0.02])
+    nodes = stack(2, 3, 2, 3, 3, 0.7, outer=(V, V), u_bc=np.tile(u0, (6, 1)))
+    ref = []
+    for nd in nodes:
+        nx, ny, nz = nd[0].shape
+        nd[0].init_equilibrium(np.ones((nz, ny, nx)), np.broadcast_to(u0[:, None, None, None], (3, nz, ny, nx)).copy())
+        ref.append(nd[0].get_pdfs())
+    oracle.refine_tree_step(nodes, 3)
+    for nd, r in zip(nodes, ref):
+        np.testing.assert_allclose(nd[0].get_pdfs(), r, rtol=0, atol=2e-15)
+
+
+def test_refine_tree_poiseuille_exact_across_four_interfaces():
+    """Fine (8 rows, 1/4 cells) / medium (8 rows, 1/2) / coarse (8) / medium /
+    fine: the steady force-driven profile is the parabola of the physical
+    height 20 on every level, to roundoff."""
+    tau, F = 0.8, 1e-5
+    nodes = stack(1, 8, 1, 8, 8, tau, (F, 0, 0))
+    for nd in nodes:
+        nx, ny, nz = nd[0].shape
+        nd[0].init_equilibrium(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    oracle.refine_tree_step(nodes, 12000)
+    H, nu = 2 + 4 + 8 + 4 + 2, (tau - 0.5) / 3
+    placed = [(nodes[3][0], 0.0, 0.25), (nodes[1][0], 2.0, 0.5), (nodes[0][0], 6.0, 1.0), (nodes[2][0], 14.0, 0.5),
+              (nodes[4][0], 18.0, 0.25)]
+    for s, y0, h in placed:
+        _, u = s.moments()
+        y = y0 + (np.arange(s.shape[1]) + 0.5) * h
+        exact = F / (2 * nu) * y * (H - y)
+        assert np.abs(u[0][0, :, 0] - exact).max() <= 1e-10 * exact.max()
+
+
+def _emulate_tree(specs, pdfs, q):
+    """One step of node 0 of a refinement tree, recursively, from
+    single-lattice oracle steps (interface faces as no-slip) and the
+    point-in-cell rules of the two-level emulation above."""
+    cvec, _, _ = oracle.velocity_set(q)
+    opp = [int(np.nonzero((cvec == -cvec[i]).all(1))[0][0]) for i in range(q)]
+
+    def advance(k):
+        shape, tau, F, lo, hi = specs[k]
+        s = oracle.Sim(q, shape, bc=(P, P, NS, NS, P, P), tau=tau, force=F)
+        s.set_pdfs(pdfs[k])
+        s.step(1)
+        pdfs[k] = s.get_pdfs()
+        nxc, nyc, nzc = shape
+        sums = {}
+        for side, child in ((0, lo), (1, hi)):
+            if child is None:
+                continue
+            dy = 1 if side else -1
+            yc = nyc - 1 if side else 0
+            yf = 0 if side else specs[child][0][1] - 1
+            cnew = pdfs[k].copy()
+
+            def cell(xf, zf, j, sign):
+                px = ((xf + 0.5) / 2 + sign * cvec[j][0] * 0.5) % nxc
+                pz = ((zf + 0.5) / 2 + sign * cvec[j][2] * 0.5) % nzc
+                return int(math.floor(px)), int(math.floor(pz))
+
+            acc = np.zeros((q, nzc, nxc))
+            for sub in range(2):
+                advance(child)
+                f = pdfs[child]
+                for i in range(q):
+                    if cvec[i][1] != -dy:
+                        continue
+                    for zf in range(2 * nzc):
+                        for xf in range(2 * nxc):
+                            X, Z = cell(xf, zf, i, +1)
+                            acc[i, Z, X] += f[opp[i], zf, yf, xf] / 8.0
+                for j in range(q):
+                    if cvec[j][1] != dy:
+                        continue
+                    for zf in range(2 * nzc):
+                        for xf in range(2 * nxc):
+                            X, Z = cell(xf, zf, j, -1)
+                            f[j, zf, yf, xf] = cnew[opp[j], Z, yc, X]
+            sums[side] = (yc, dy, acc)
+        for side, (yc, dy, acc) in sums.items():
+            for i in range(q):
+                if cvec[i][1] == -dy:
+                    pdfs[k][i, :, yc, :] = acc[i]
+
+    advance(0)
+    return pdfs
+
+
+def test_refine_tree_matches_brute_force_recursion():
+    q, tau, F = 19, 0.7, np.array([1e-4, -2e-5, 3e-5])
+    nodes = stack(2, 3, 1, 3, 3, tau, tuple(F), q=q)
+    for k, nd in enumerate(nodes):
+        random_state(nd[0], 60 + k)
+    specs = []
+    for nd, d in zip(nodes, DEPTH):
+        s = nd[0]
+        specs.append((s.shape, 0.5 + 2 ** d * (tau - 0.5), tuple(F / 2 ** d), nd[1], nd[2]))
+    ref = _emulate_tree(specs, [nd[0].get_pdfs() for nd in nodes], q)
+    oracle.refine_tree_step(nodes, 1)
+    for nd, r in zip(nodes, ref):
+        np.testing.assert_allclose(nd[0].get_pdfs(), r, rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("case", ["child_before_parent", "two_parents", "orphan", "face_without_child",
+                                  "child_facing_parent"])
+def test_refine_tree_rejects_malformed_trees(case):
+    nodes = stack(2, 3, 1, 3, 3, 0.7)
+    if case == "child_before_parent":
+        nodes = [nodes[1], nodes[0]] + nodes[2:]
+    elif case == "two_parents":
+        nodes[2] = (nodes[2][0], None, 3)
+    elif case == "orphan":
+        nodes[1] = (nodes[1][0], None, None)
+    elif case == "face_without_child":
+        nodes[0] = (nodes[0][0], 1, None)
+        nodes[2] = (nodes[2][0], None, None)
+        nodes = nodes[:2] + nodes[3:4]
+    elif case == "child_facing_parent":
+        nodes[1] = (nodes[1][0], None, 3)
+    with pytest.raises(ValueError):
+        oracle.refine_tree_step(nodes, 1)
