@@ -390,6 +390,35 @@ int lbm_refine_work_bytes(const lbm_domain *coarse, int stencil, size_t *bytes);
 int lbm_refine_step(lbm_ctx *coarse, lbm_ctx *fine_lo, lbm_ctx *fine_hi, void *work_dev, size_t work_bytes,
                     int64_t n);
 
+/* Hierarchies of 2:1 levels (the paper's refinement trees, Section 3): each
+ * level may be refined again, so the levels form a stack along y whose
+ * cell size halves from level to level away from the coarsest one, e.g.
+ * fine2 | fine1 | coarse | fine1 | fine2.  A node is a lattice and the
+ * indices (into the node array, -1 for none) of the finer lattices below
+ * (fine_lo) and above (fine_hi) it; nodes[0] is the coarsest lattice and
+ * every child comes after its parent and has exactly one.  Each parent and
+ * child pair satisfies the conditions of lbm_refine_step, and a y face is an
+ * interface exactly where it meets another level (so a child has no child on
+ * its parent's side).  work_dev / work_bytes: the node's work buffer as for
+ * lbm_refine_step, needed by nodes with a child (distinct buffers; ignored
+ * otherwise).  The node array is read during the call only. */
+typedef struct lbm_refine_node {
+    lbm_ctx *ctx;
+    int32_t fine_lo, fine_hi;
+    void *work_dev;
+    size_t work_bytes;
+} lbm_refine_node;
+
+/* Advance nodes[0] n >= 0 steps; a node at depth d takes 2^d steps per step
+ * of nodes[0]: each node takes its own step, then for each child the child
+ * advances two steps (recursively, each followed by the exchange of
+ * lbm_refine_step), then the node's interface rows take the summed packets.
+ * 1 <= count <= 4096.  Errors as for lbm_refine_step, reported on nodes[0]
+ * (on the thread's global error text for a NULL array or context); a
+ * failed launch leaves every level part way through a step.
+ * lbm_refine_step(c, lo, hi, ...) is this call on the nodes {c, lo, hi}. */
+int lbm_refine_tree_step(const lbm_refine_node *nodes, int32_t count, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/lbm.h"
 #include "internal.h"
@@ -660,85 +661,141 @@ int lbm_refine_work_bytes(const lbm_domain *d, int stencil, size_t *bytes)
 
 static bool rel_close(double a, double b) { return fabs(a - b) <= 1e-9 * fmax(fabs(a), fabs(b)) + 1e-300; }
 
-// Does fine lattice f fit coarse lattice c on side `above`?  Writes the
-// reason into c's error text.
-static int refine_check(lbm_ctx *c, const lbm_ctx *f, int above)
+// Does node kf fit below (above = 0) or above (above = 1) node kc as its
+// 2:1 finer level?  Failures are reported on the root context.
+static int refine_check(lbm_ctx *root, int kc, const lbm_ctx *c, int kf, const lbm_ctx *f, int above)
 {
-    const char *side = above ? "fine_hi" : "fine_lo";
-    if (f->q != c->q) return fail(c, LBM_EINVAL, "refine: %s has another stencil", side);
+    const char *side = above ? "above" : "below";
+    if (f == c) return fail(root, LBM_EINVAL, "refine: node %d is its own child", kc);
+    if (f->q != c->q) return fail(root, LBM_EINVAL, "refine: node %d (%s node %d) has another stencil", kf, side, kc);
     if (f->a.nx != 2 * c->a.nx || f->a.nz != 2 * c->a.nz)
-        return fail(c, LBM_EINVAL, "refine: %s must have twice the coarse nx and nz (%d x %d, coarse %d x %d)", side,
-                    f->a.nx, f->a.nz, c->a.nx, c->a.nz);
+        return fail(root, LBM_EINVAL, "refine: node %d (%s node %d) must have twice its nx and nz (%d x %d, coarse %d x %d)",
+                    kf, side, kc, f->a.nx, f->a.nz, c->a.nx, c->a.nz);
     if (f->bc_kind[above ? 2 : 3] != LBM_BC_INTERFACE)
-        return fail(c, LBM_EINVAL, "refine: the %s face of %s facing the coarse lattice is not an interface", above ? "-y" : "+y",
-                    side);
-    if (f->bc_kind[above ? 3 : 2] == LBM_BC_INTERFACE)
-        return fail(c, LBM_EINVAL, "refine: %s has a second interface face", side);
-    if (!f->a.per[0] || !f->a.per[2]) return fail(c, LBM_EINVAL, "refine: x and z must be periodic on %s", side);
-    if (f->sp.on || f->a.et) return fail(c, LBM_EINVAL, "refine: %s must use the dense AA pattern", side);
-    if (f->coll != c->coll) return fail(c, LBM_EINVAL, "refine: %s has another collision", side);
-    if (f->cl != LBM_LES_NONE) return fail(c, LBM_EINVAL, "refine: %s has a closure", side);
-    if (f->magic_d != c->magic_d) return fail(c, LBM_EINVAL, "refine: %s has another magic parameter", side);
+        return fail(root, LBM_EINVAL, "refine: the %s face of node %d facing node %d is not an interface",
+                    above ? "-y" : "+y", kf, kc);
+    if (f->coll != c->coll) return fail(root, LBM_EINVAL, "refine: node %d has another collision than node %d", kf, kc);
+    if (f->magic_d != c->magic_d)
+        return fail(root, LBM_EINVAL, "refine: node %d has another magic parameter than node %d", kf, kc);
     if (c->coll == LBM_COLL_MRT)
         for (int k = 0; k < 5; ++k)
-            if (f->mrt_d[k] != c->mrt_d[k]) return fail(c, LBM_EINVAL, "refine: %s has other MRT ghost rates", side);
+            if (f->mrt_d[k] != c->mrt_d[k])
+                return fail(root, LBM_EINVAL, "refine: node %d has other MRT ghost rates than node %d", kf, kc);
     if (!rel_close(f->tau_d, 0.5 + 2.0 * (c->tau_d - 0.5)))
-        return fail(c, LBM_EINVAL, "refine: %s needs tau = 1/2 + 2 (tau_c - 1/2) = %.17g (got %.17g)", side,
+        return fail(root, LBM_EINVAL, "refine: node %d needs tau = 1/2 + 2 (tau_c - 1/2) = %.17g (got %.17g)", kf,
                     0.5 + 2.0 * (c->tau_d - 0.5), f->tau_d);
     for (int k = 0; k < 3; ++k)
         if (!(rel_close(f->force_d[k], 0.5 * c->force_d[k]) || (f->force_d[k] == 0.0 && c->force_d[k] == 0.0)))
-            return fail(c, LBM_EINVAL, "refine: %s needs force = coarse force / 2", side);
-    if (f->stream != c->stream) return fail(c, LBM_EINVAL, "refine: %s runs on another stream", side);
-    if (f == c) return fail(c, LBM_EINVAL, "refine: %s is the coarse lattice", side);
+            return fail(root, LBM_EINVAL, "refine: node %d needs force = force of node %d / 2", kf, kc);
+    if (f->stream != c->stream) return fail(root, LBM_EINVAL, "refine: node %d runs on another stream", kf);
+    return LBM_OK;
+}
+
+// Advance node k one step: its own step, then per child the recorded packets,
+// two child steps (recursively) each followed by add and fill, and finally
+// the node's interface rows from the sums.
+static int refine_advance(const lbm_refine_node *nodes, int k)
+{
+    lbm_ctx *c = nodes[k].ctx;
+    int rc = step_once(c);
+    if (rc) return rc;
+    const size_t plane = refine_plane_floats(c->q, c->a.nx, c->a.nz);
+    float *buf = (float *)nodes[k].work_dev;
+    const int child[2] = {nodes[k].fine_lo, nodes[k].fine_hi};
+    for (int side = 0; side < 2; ++side) {
+        if (child[side] < 0) continue;
+        lbm_ctx *f = nodes[child[side]].ctx;
+        const int dy = side ? 1 : -1, yc = side ? c->a.ny - 1 : 0, yf = side ? 0 : f->a.ny - 1;
+        float *cout = buf + (size_t)(2 * side) * plane, *acc = cout + plane;
+        HIPCHECK(c, launch_refine_record(c->a, c->q, c->st, yc, dy, cout, c->stream), "refine record");
+        for (int sub = 0; sub < 2; ++sub) {
+            if ((rc = refine_advance(nodes, child[side]))) return rc;
+            HIPCHECK(c, launch_refine_add(f->a, f->q, f->st, yf, dy, c->a.nx, c->a.nz, sub == 0, acc, c->stream),
+                     "refine add");
+            HIPCHECK(c, launch_refine_fill_fine(f->a, f->q, f->st, yf, dy, c->a.nx, c->a.nz, cout, c->stream),
+                     "refine fill fine");
+        }
+    }
+    for (int side = 0; side < 2; ++side) {
+        if (child[side] < 0) continue;
+        const int dy = side ? 1 : -1, yc = side ? c->a.ny - 1 : 0;
+        HIPCHECK(c, launch_refine_fill_coarse(c->a, c->q, c->st, yc, dy, buf + (size_t)(2 * side + 1) * plane, c->stream),
+                 "refine fill coarse");
+    }
+    return LBM_OK;
+}
+
+int lbm_refine_tree_step(const lbm_refine_node *nodes, int32_t count, int64_t n)
+{
+    if (!nodes || count < 1 || count > 4096) return fail(nullptr, LBM_EINVAL, "refine: need 1 to 4096 nodes");
+    for (int k = 0; k < count; ++k)
+        if (!nodes[k].ctx) return fail(nullptr, LBM_EINVAL, "refine: node %d has no context", k);
+    lbm_ctx *root = nodes[0].ctx;
+    if (n < 0) return fail(root, LBM_EINVAL, "refine: step count must be >= 0");
+    std::vector<int> parents(count, 0), up(count, 0);  // face toward the parent (2 or 3), 0 for none
+    for (int k = 0; k < count; ++k) {
+        lbm_ctx *c = nodes[k].ctx;
+        if (!c->a.per[0] || !c->a.per[2]) return fail(root, LBM_EINVAL, "refine: x and z must be periodic on node %d", k);
+        if (c->sp.on || c->a.et) return fail(root, LBM_EINVAL, "refine: node %d must use the dense AA pattern", k);
+        if (c->cl != LBM_LES_NONE) return fail(root, LBM_EINVAL, "refine: node %d has a closure", k);
+        if (c->coll == LBM_COLL_HRR) return fail(root, LBM_EINVAL, "refine: HRR is not supported");
+        const int child[2] = {nodes[k].fine_lo, nodes[k].fine_hi};
+        for (int side = 0; side < 2; ++side) {
+            if (child[side] < 0) continue;
+            if (child[side] <= k || child[side] >= count)
+                return fail(root, LBM_EINVAL, "refine: child %d of node %d must come after it", child[side], k);
+            ++parents[child[side]];
+            up[child[side]] = side ? 2 : 3;  // a lower child meets its parent with its +y face
+            const int rc = refine_check(root, k, c, child[side], nodes[child[side]].ctx, side);
+            if (rc) return rc;
+        }
+        if (child[0] >= 0 || child[1] >= 0) {
+            const size_t need = 4 * refine_plane_floats(c->q, c->a.nx, c->a.nz) * sizeof(float);
+            if (!nodes[k].work_dev || ((uintptr_t)nodes[k].work_dev & 3) != 0)
+                return fail(root, LBM_EINVAL, "refine: node %d needs a 4-byte aligned work buffer", k);
+            if (nodes[k].work_bytes < need)
+                return fail(root, LBM_EINVAL, "refine: node %d work buffer too small: %zu < %zu bytes", k,
+                            nodes[k].work_bytes, need);
+        }
+    }
+    for (int k = 1; k < count; ++k)
+        if (parents[k] != 1) return fail(root, LBM_EINVAL, "refine: node %d has %d parents", k, parents[k]);
+    for (int k = 0; k < count; ++k) {
+        const int child[2] = {nodes[k].fine_lo, nodes[k].fine_hi};
+        for (int side = 0; side < 2; ++side) {
+            const int face = side ? 3 : 2;
+            const bool has = child[side] >= 0, toward = up[k] == face;
+            if (has && toward) return fail(root, LBM_EINVAL, "refine: node %d has a child on its parent's side", k);
+            if ((nodes[k].ctx->bc_kind[face] == LBM_BC_INTERFACE) != (has || toward))
+                return fail(root, LBM_EINVAL, "refine: node %d: a y face is an interface exactly where it meets another level",
+                            k);
+        }
+    }
+    for (int64_t t = 0; t < n; ++t) {
+        const int rc = refine_advance(nodes, 0);
+        if (rc) return rc;
+    }
     return LBM_OK;
 }
 
 int lbm_refine_step(lbm_ctx *c, lbm_ctx *lo, lbm_ctx *hi, void *work_dev, size_t work_bytes, int64_t n)
 {
     if (!c) return fail(nullptr, LBM_EINVAL, "refine: coarse context is NULL");
-    if (n < 0) return fail(c, LBM_EINVAL, "refine: step count must be >= 0");
-    if ((c->bc_kind[2] == LBM_BC_INTERFACE) != (lo != nullptr) || (c->bc_kind[3] == LBM_BC_INTERFACE) != (hi != nullptr))
-        return fail(c, LBM_EINVAL, "refine: a fine lattice is given exactly where the coarse y face is an interface");
     if (!lo && !hi) return fail(c, LBM_EINVAL, "refine: no fine lattice");
     if (lo && hi && lo == hi) return fail(c, LBM_EINVAL, "refine: fine_lo and fine_hi are the same lattice");
-    if (!c->a.per[0] || !c->a.per[2]) return fail(c, LBM_EINVAL, "refine: x and z must be periodic on the coarse lattice");
-    if (c->sp.on || c->a.et) return fail(c, LBM_EINVAL, "refine: the coarse lattice must use the dense AA pattern");
-    if (c->cl != LBM_LES_NONE) return fail(c, LBM_EINVAL, "refine: the coarse lattice has a closure");
-    if (c->coll == LBM_COLL_HRR) return fail(c, LBM_EINVAL, "refine: HRR is not supported");
-    int rc;
-    if (lo && (rc = refine_check(c, lo, 0))) return rc;
-    if (hi && (rc = refine_check(c, hi, 1))) return rc;
-    const size_t plane = refine_plane_floats(c->q, c->a.nx, c->a.nz);
     if (!work_dev) return fail(c, LBM_EINVAL, "refine: work buffer is NULL");
-    if (((uintptr_t)work_dev & 3) != 0) return fail(c, LBM_EINVAL, "refine: work buffer must be 4-byte aligned");
-    if (work_bytes < 4 * plane * sizeof(float))
-        return fail(c, LBM_EINVAL, "refine: work buffer too small: %zu < %zu bytes", work_bytes, 4 * plane * sizeof(float));
-    float *buf = (float *)work_dev;
-    lbm_ctx *fl[2] = {lo, hi};
-    for (int64_t t = 0; t < n; ++t) {
-        if ((rc = step_once(c))) return rc;
-        for (int k = 0; k < 2; ++k) {
-            lbm_ctx *f = fl[k];
-            if (!f) continue;
-            const int dy = k ? 1 : -1, yc = k ? c->a.ny - 1 : 0, yf = k ? 0 : f->a.ny - 1;
-            float *cout = buf + (size_t)(2 * k) * plane, *acc = cout + plane;
-            HIPCHECK(c, launch_refine_record(c->a, c->q, c->st, yc, dy, cout, c->stream), "refine record");
-            for (int sub = 0; sub < 2; ++sub) {
-                if ((rc = step_once(f))) return fail(c, rc, "refine: fine step: %s", f->err);
-                HIPCHECK(c, launch_refine_add(f->a, f->q, f->st, yf, dy, c->a.nx, c->a.nz, sub == 0, acc, c->stream),
-                         "refine add");
-                HIPCHECK(c, launch_refine_fill_fine(f->a, f->q, f->st, yf, dy, c->a.nx, c->a.nz, cout, c->stream),
-                         "refine fill fine");
-            }
-        }
-        for (int k = 0; k < 2; ++k) {
-            if (!fl[k]) continue;
-            const int dy = k ? 1 : -1, yc = k ? c->a.ny - 1 : 0;
-            HIPCHECK(c, launch_refine_fill_coarse(c->a, c->q, c->st, yc, dy, buf + (size_t)(2 * k + 1) * plane, c->stream),
-                     "refine fill coarse");
-        }
+    lbm_refine_node nodes[3];
+    int count = 1;
+    nodes[0] = {c, -1, -1, work_dev, work_bytes};
+    if (lo) {
+        nodes[count] = {lo, -1, -1, nullptr, 0};
+        nodes[0].fine_lo = count++;
     }
-    return LBM_OK;
+    if (hi) {
+        nodes[count] = {hi, -1, -1, nullptr, 0};
+        nodes[0].fine_hi = count++;
+    }
+    return lbm_refine_tree_step(nodes, count, n);
 }
 
 }  // extern "C"

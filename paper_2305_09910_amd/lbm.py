@@ -33,7 +33,7 @@ EXPORTED = [
     "lbm_moments", "lbm_totals", "lbm_state_bytes", "lbm_save_state", "lbm_load_state",
     "lbm_set_closure_weights", "lbm_closure_fallbacks", "lbm_box_filter4", "lbm_closure_dataset",
     "lbm_mlp_forward", "lbm_mlp_work_bytes", "lbm_mlp_loss_grad", "lbm_mlp_loss_grad_noalloc", "lbm_mlp_adam",
-    "lbm_stream_copy", "lbm_refine_work_bytes", "lbm_refine_step", "lbm_closure_features",
+    "lbm_stream_copy", "lbm_refine_work_bytes", "lbm_refine_step", "lbm_refine_tree_step", "lbm_closure_features",
 ]
 
 
@@ -56,6 +56,11 @@ class Domain(ctypes.Structure):
         ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p),
     ]
+
+
+class RefineNode(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("fine_lo", ctypes.c_int32), ("fine_hi", ctypes.c_int32),
+                ("work_dev", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -100,6 +105,7 @@ def lib():
             "lbm_stream_copy": (ctypes.c_int, [P, P, SZ, P]),
             "lbm_refine_work_bytes": (ctypes.c_int, [DP, ctypes.c_int, ctypes.POINTER(SZ)]),
             "lbm_refine_step": (ctypes.c_int, [P, P, P, P, SZ, I64]),
+            "lbm_refine_tree_step": (ctypes.c_int, [ctypes.POINTER(RefineNode), I32, I64]),
             "lbm_closure_features": (ctypes.c_int, [P, P]),
         }
         for name, (res, args) in sig.items():
@@ -390,13 +396,36 @@ def refine_step(coarse, fine_lo=None, fine_hi=None, n=1):
     and each fine Lattice (below / above it, None where the coarse y face is
     not an "interface" face) 2n steps, exchanging the packets that cross the
     interfaces.  The work buffer is allocated once per coarse lattice."""
-    torch = _torch()
-    work = getattr(coarse, "_refine_work", None)
-    if work is None:
-        nbytes = ctypes.c_size_t(0)
-        _check(lib().lbm_refine_work_bytes(ctypes.byref(coarse.domain), coarse.q, ctypes.byref(nbytes)))
-        work = torch.empty(nbytes.value, dtype=torch.uint8, device=coarse.device)
-        coarse._refine_work = work
+    work = _refine_work(coarse)
     lo = fine_lo._h if fine_lo is not None else None
     hi = fine_hi._h if fine_hi is not None else None
     _check(lib().lbm_refine_step(coarse._h, lo, hi, work.data_ptr(), work.numel(), int(n)), coarse._h)
+
+
+def _refine_work(lat):
+    """The refinement work buffer of a parent Lattice (allocated once)."""
+    work = getattr(lat, "_refine_work", None)
+    if work is None:
+        nbytes = ctypes.c_size_t(0)
+        _check(lib().lbm_refine_work_bytes(ctypes.byref(lat.domain), lat.q, ctypes.byref(nbytes)))
+        work = _torch().empty(nbytes.value, dtype=_torch().uint8, device=lat.device)
+        lat._refine_work = work
+    return work
+
+
+def refine_tree_step(nodes, n=1):
+    """lbm_refine_tree_step: advance a hierarchy of 2:1 levels.  nodes is a
+    sequence of (Lattice, fine_lo, fine_hi) with the indices of the finer
+    lattices below / above each one (None for none), nodes[0] the coarsest;
+    it takes n steps and a lattice at depth d 2^d n steps.  Parents' work
+    buffers are allocated once per Lattice."""
+    arr = (RefineNode * len(nodes))()
+    for k, (lat, lo, hi) in enumerate(nodes):
+        arr[k].ctx = lat._h
+        arr[k].fine_lo = -1 if lo is None else int(lo)
+        arr[k].fine_hi = -1 if hi is None else int(hi)
+        if lo is not None or hi is not None:
+            work = _refine_work(lat)
+            arr[k].work_dev = work.data_ptr()
+            arr[k].work_bytes = work.numel()
+    _check(lib().lbm_refine_tree_step(arr, len(nodes), int(n)), nodes[0][0]._h if nodes else None)

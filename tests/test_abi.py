@@ -245,6 +245,19 @@ def test_refine_work_bytes(L):
     assert L.lbm_refine_step(None, None, None, None, 0, 1) == lbm.LBM_EINVAL
 
 
+def test_refine_tree_rejects_without_device(L):
+    """A NULL node array, a count outside 1..4096 and a node without a context
+    are rejected on the thread's error text before any device call."""
+    assert L.lbm_refine_tree_step(None, 1, 1) == lbm.LBM_EINVAL
+    nodes = (lbm.RefineNode * 2)()
+    for count in (0, -1, 4097):
+        assert L.lbm_refine_tree_step(nodes, count, 1) == lbm.LBM_EINVAL
+    nodes[0].fine_lo = nodes[0].fine_hi = -1
+    assert L.lbm_refine_tree_step(nodes, 1, 1) == lbm.LBM_EINVAL
+    assert b"no context" in L.lbm_last_error(None)
+    assert ctypes.sizeof(lbm.RefineNode) == 32  # pointer, two int32, pointer, size_t
+
+
 def test_hrr_workspace_holds_two_velocity_fields(L):
     """HRR keeps the previous and the current velocity field (3 FP32 each per
     cell) next to the populations."""
