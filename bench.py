@@ -376,115 +376,143 @@ def gpu_l2(form, refs):
 
 
 # ---------------------------------------------------------------------------
-# 2:1 refinement: a wall-refined channel (fine levels at both walls, a coarse
-# core); one coarse and two fine steps per call of lbm_refine_step
+# 2:1 refinement: a wall-refined channel (a coarse core between stacks of ever
+# finer levels at both walls); each level at depth d takes 2^d steps per
+# coarsest step (lbm_refine_tree_step)
 # ---------------------------------------------------------------------------
 REFINED = "refined_channel_512x128x256_d3q19_f32"
-REFINED_L2_COPY = (64, 16, 32, 8, 100)  # coarse nx, ny, nz; fine ny; coarse steps
+REFINED_TREE = "refined_tree_channel_256x64x128_d3q19_f32"
+REFINED_FORMS = {  # coarse nx, ny, nz; ny of the levels at depth 1, 2, ...
+    REFINED: (512, 128, 256, (64,)),
+    REFINED_TREE: (256, 64, 128, (32, 32)),
+}
+REFINED_L2_COPY = {  # the same stacks scaled down, and the coarsest steps they run against the oracle
+    REFINED: (64, 16, 32, (8,), 100),
+    REFINED_TREE: (32, 16, 16, (8, 8), 100),
+}
+REFINED_NOTES = {
+    REFINED: "2:1 refinement: fine levels at both walls, coarse core; MLUPS count every level's cell updates "
+             "(fine cells twice per coarse step)",
+    REFINED_TREE: "hierarchy of 2:1 levels: fine (4x) / medium (2x) / coarse / medium / fine along y; MLUPS count "
+                  "every level's cell updates (2^depth per coarsest step)",
+}
 
 
-def refined_cfgs(nxc=512, nyc=128, nzc=256, nyf=64, storage="f32"):
-    """Coarse core (nxc, nyc, nzc) between fine levels (2 nxc, nyf, 2 nzc) at
-    the walls: channel height nyc + nyf coarse cells, body force for a
-    centreline velocity of 0.05, tau_c = 0.51 (tau_f = 0.52, F_f = F_c / 2)."""
-    H = nyc + nyf
+def refined_nodes(nxc, nyc, nzc, nys, storage="f32"):
+    """A coarse core (nxc, nyc, nzc) between stacks of finer levels at both
+    walls: the level at depth d (1, 2, ...) has (2^d nxc, nys[d-1], 2^d nzc)
+    cells of size 2^-d coarse cells, tau_d = 1/2 + 2^d (tau_c - 1/2) and force
+    F_c / 2^d, with tau_c = 0.51 and the body force of a centreline velocity of
+    0.05.  Returned in tree order (coarse, then the lower and upper level of
+    each depth), each with the indices of its finer neighbours below / above."""
+    D = len(nys)
+    H = nyc + sum(2 * ny / 2 ** d for d, ny in enumerate(nys, 1))
     tau = 0.51
     F = 8 * ((tau - 0.5) / 3) * 0.05 / H ** 2
-    per = ("periodic", "periodic")
-    mk = lambda name, shape, bc, t, f, y0, h: dict(name=name, shape=shape, q=19, tau=t, force=(f, 0.0, 0.0), bc=bc,
-                                                  u_bc=None, solid=None, storage=storage, closure="none",
-                                                  y0=y0, h=h, height=H)
-    return {"lo": mk("lo", (2 * nxc, nyf, 2 * nzc), per + ("noslip", "interface") + per, 0.5 + 2 * (tau - 0.5), F / 2,
-                     0.0, 0.5),
-            "c": mk("c", (nxc, nyc, nzc), per + ("interface", "interface") + per, tau, F, nyf / 2, 1.0),
-            "hi": mk("hi", (2 * nxc, nyf, 2 * nzc), per + ("interface", "noslip") + per, 0.5 + 2 * (tau - 0.5), F / 2,
-                     nyf / 2 + nyc, 0.5)}
+    per, I = ("periodic", "periodic"), "interface"
+
+    def mk(name, depth, shape, faces, lo, hi):
+        return dict(name=name, depth=depth, shape=shape, q=19, tau=0.5 + 2 ** depth * (tau - 0.5),
+                    force=(F / 2 ** depth, 0.0, 0.0), bc=per + faces + per, storage=storage, lo=lo, hi=hi, height=H,
+                    h=2.0 ** -depth)
+
+    nodes = [mk("c", 0, (nxc, nyc, nzc), (I, I) if D else ("noslip", "noslip"), 1 if D else None, 2 if D else None)]
+    for d, ny in enumerate(nys, 1):
+        shape, deeper = (2 ** d * nxc, ny, 2 ** d * nzc), d < D
+        nodes.append(mk(f"lo{d}", d, shape, (I if deeper else "noslip", I), 2 * d + 1 if deeper else None, None))
+        nodes.append(mk(f"hi{d}", d, shape, (I, I if deeper else "noslip"), None, 2 * d + 2 if deeper else None))
+    # first rows and seeds from the bottom wall up
+    order = [2 * d - 1 for d in range(D, 0, -1)] + [0] + [2 * d for d in range(1, D + 1)]
+    y = 0.0
+    for k, i in enumerate(order):
+        nodes[i]["y0"], nodes[i]["seed"] = y, 1234 + k
+        y += nodes[i]["shape"][1] * nodes[i]["h"]
+    return nodes
 
 
-def refined_fields(cfg, seed):
+def refined_fields(cfg):
     from paper_2305_09910_amd import inputs
     nx, ny, nz = cfg["shape"]
-    return inputs.channel_level(nx, ny, nz, cfg["y0"], cfg["h"], cfg["height"], 0.05, 0.05, seed=seed)
+    return inputs.channel_level(nx, ny, nz, cfg["y0"], cfg["h"], cfg["height"], 0.05, 0.05, seed=cfg["seed"])
 
 
-def make_refined(cfgs):
+def make_refined(nodes):
+    """GPU lattices in tree order as (Lattice, lo, hi) for refine_tree_step."""
     from paper_2305_09910_amd import lbm
-    lats = {}
-    for k, (name, cfg) in enumerate(cfgs.items()):
+    tree = []
+    for cfg in nodes:
         lat = lbm.Lattice(cfg["shape"], q=19, tau=cfg["tau"], force=cfg["force"], bc=cfg["bc"], storage=cfg["storage"])
-        lat.init_equilibrium(*refined_fields(cfg, 1234 + k))
-        lats[name] = lat
-    return lats
+        lat.init_equilibrium(*refined_fields(cfg))
+        tree.append((lat, cfg["lo"], cfg["hi"]))
+    return tree
 
 
-def time_refined(steps, warmup):
-    """Cell updates per second over all levels (coarse cells once, fine cells
-    twice per coarse step), and the share of the time spent outside the
-    levels' own step kernels (the exchange kernels and their launches)."""
+def time_refined(key, steps, warmup):
+    """Cell updates per second over all levels (a level at depth d 2^d times
+    per coarsest step), and the share of the time spent outside the levels'
+    own step kernels (the exchange kernels and their launches)."""
     import torch
     from paper_2305_09910_amd import lbm
-    cfgs = refined_cfgs()
-    lats = make_refined(cfgs)
-    c, lo, hi = lats["c"], lats["lo"], lats["hi"]
-    lbm.refine_step(c, lo, hi, warmup)
+    nodes = refined_nodes(*REFINED_FORMS[key])
+    tree = make_refined(nodes)
+    stream = tree[0][0].stream
+    lbm.refine_tree_step(tree, warmup)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    a.record(c.stream)
-    lbm.refine_step(c, lo, hi, steps)
-    b.record(c.stream)
+    a.record(stream)
+    lbm.refine_tree_step(tree, steps)
+    b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = a.elapsed_time(b)
     # the same level steps without the exchange (their states advance further; timing only)
     a2, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a2.record(c.stream)
+    a2.record(stream)
     for _ in range(steps):
-        c.step(1)
-        lo.step(2)
-        hi.step(2)
-    b2.record(c.stream)
+        for (lat, _, _), cfg in zip(tree, nodes):
+            lat.step(2 ** cfg["depth"])
+    b2.record(stream)
     torch.cuda.synchronize()
     ms_levels = a2.elapsed_time(b2)
-    ncs = [cfgs[k]["shape"][0] * cfgs[k]["shape"][1] * cfgs[k]["shape"][2] for k in ("c", "lo", "hi")]
-    updates = ncs[0] + 2 * (ncs[1] + ncs[2])
+    updates = sum(cfg["shape"][0] * cfg["shape"][1] * cfg["shape"][2] * 2 ** cfg["depth"] for cfg in nodes)
     nb = bytes_per_cell(19, BYTES["f32"])
-    plane = cfgs["c"]["shape"][0] * cfgs["c"]["shape"][2]
-    # per side and coarse step, 5 crossing directions: record 8 B, 2 adds of 20 B, 2 fine fills of
-    # 4 x 8 B, one coarse fill of 8 B per coarse interface cell and direction
-    xbytes = 2 * 5 * plane * (8 + 2 * 20 + 2 * 32 + 8)
+    # per child and parent step, 5 crossing directions, two exchanges per parent interface cell and
+    # direction: 4 fine slots read and written and the parent's slot read (36 B) in each, then the
+    # sum written (4 B) or read with the parent's slot written (8 B)
+    xbytes = sum(2 ** cfg["depth"] * 5 * cfg["shape"][0] * cfg["shape"][2] * (36 + 4 + 36 + 8)
+                 for cfg in nodes for child in (cfg["lo"], cfg["hi"]) if child is not None)
     moved = updates * nb + xbytes
-    del lats, c, lo, hi
+    del tree
     torch.cuda.empty_cache()
     return {"mlups": round(updates * steps / wall / 1e6, 1), "kernel_mlups": round(updates * steps / (ms * 1e-3) / 1e6, 1),
-            "cell_updates_per_coarse_step": updates, "levels": {k: cfgs[k]["shape"] for k in ("lo", "c", "hi")},
+            "cell_updates_per_coarse_step": updates, "levels": {cfg["name"]: cfg["shape"] for cfg in nodes},
             "bytes_per_coarse_step": moved, "achieved_gbs": round(moved * steps / (ms * 1e-3) / 1e9, 1),
             "roofline_frac": round(moved * steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "exchange_share": round(max(0.0, 1 - ms_levels / ms), 4), "us_per_coarse_step": round(1e3 * ms / steps, 1)}
 
 
-def refined_l2():
-    """Velocity L2 error of the refined form's copy (coarse 64x16x32, fine
-    128x8x64 at both walls, 100 coarse steps) against the oracle, per level."""
+def refined_l2(key):
+    """Velocity L2 error of a refined form's scaled-down copy against the
+    oracle after its coarsest steps, per level."""
     import oracle
     from paper_2305_09910_amd import lbm
-    nxc, nyc, nzc, nyf, steps = REFINED_L2_COPY
-    cfgs = refined_cfgs(nxc, nyc, nzc, nyf)
+    nxc, nyc, nzc, nys, steps = REFINED_L2_COPY[key]
+    nodes = refined_nodes(nxc, nyc, nzc, nys)
     bcs = {"periodic": oracle.BC_PERIODIC, "noslip": oracle.BC_NOSLIP, "interface": oracle.BC_INTERFACE}
-    orc = {}
-    for k, (name, cfg) in enumerate(cfgs.items()):
+    orc = []
+    for cfg in nodes:
         o = oracle.Sim(19, cfg["shape"], bc=tuple(bcs[b] for b in cfg["bc"]), tau=cfg["tau"], force=cfg["force"])
-        o.init_equilibrium(*refined_fields(cfg, 1234 + k))
-        orc[name] = o
-    oracle.refine_step(orc["c"], orc["lo"], orc["hi"], steps)
-    lats = make_refined(cfgs)
-    lbm.refine_step(lats["c"], lats["lo"], lats["hi"], steps)
+        o.init_equilibrium(*refined_fields(cfg))
+        orc.append((o, cfg["lo"], cfg["hi"]))
+    oracle.refine_tree_step(orc, steps)
+    tree = make_refined(nodes)
+    lbm.refine_tree_step(tree, steps)
     out = {}
-    for name in ("lo", "c", "hi"):
-        ug = lats[name].moments()[1].cpu().numpy()
-        out[name] = float(f"{velocity_l2(ug, orc[name].moments()[1]):.3g}")
-    return {"value": max(out.values()), "per_level": out, "copy": f"coarse {nxc}x{nyc}x{nzc}, fine {2 * nxc}x{nyf}x"
-            f"{2 * nzc} at both walls", "steps": steps}
+    for (g, _, _), (o, _, _), cfg in zip(tree, orc, nodes):
+        out[cfg["name"]] = float(f"{velocity_l2(g.moments()[1].cpu().numpy(), o.moments()[1]):.3g}")
+    levels = ", ".join(f"{c['name']} {c['shape'][0]}x{c['shape'][1]}x{c['shape'][2]}" for c in nodes)
+    return {"value": max(out.values()), "per_level": out, "copy": levels, "steps": steps}
 
 
 PAPER_CONTEXT = {
@@ -561,7 +589,7 @@ def main():
     ap.add_argument("--form-steps", type=int, default=300)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy this many MiB once with the library's copy kernel (counter calibration)")
-    ap.add_argument("--only-form", choices=[HEADLINE] + FORMS + [REFINED], default=None,
+    ap.add_argument("--only-form", choices=[HEADLINE] + FORMS + list(REFINED_FORMS), default=None,
                     help="time only this form for --form-steps steps (for profiling); prints no JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -585,9 +613,9 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
 
-    if args.only_form == REFINED:
-        log(f"[bench] form {REFINED}, {args.form_steps} coarse steps")
-        log(f"[bench]   {time_refined(args.form_steps, 20)}")
+    if args.only_form in REFINED_FORMS:
+        log(f"[bench] form {args.only_form}, {args.form_steps} coarse steps")
+        log(f"[bench]   {time_refined(args.only_form, args.form_steps, 20)}")
         return
     if args.only_form:
         log(f"[bench] form {args.only_form}, {args.form_steps} steps")
@@ -620,22 +648,23 @@ def main():
             if key in NOTES:
                 forms[key]["note"] = NOTES[key]
             log(f"[bench]   {forms[key]}")
-        log(f"[bench] form {REFINED}, {fs} coarse steps")
-        forms[REFINED] = time_refined(fs, 20)
-        forms[REFINED]["frac_of_copy"] = round(forms[REFINED]["achieved_gbs"] / bs, 4) if bs else None
-        forms[REFINED]["note"] = ("2:1 refinement: fine levels at both walls, coarse core; MLUPS count every "
-                                  "level's cell updates (fine cells twice per coarse step)")
-        log(f"[bench]   {forms[REFINED]}")
+        for key in REFINED_FORMS:
+            log(f"[bench] form {key}, {fs} coarse steps")
+            forms[key] = time_refined(key, fs, 20)
+            forms[key]["frac_of_copy"] = round(forms[key]["achieved_gbs"] / bs, 4) if bs else None
+            forms[key]["note"] = REFINED_NOTES[key]
+            log(f"[bench]   {forms[key]}")
 
     cpu, l2 = None, {}
     if not args.no_cpu_baseline:
         log("[bench] oracle leg: cpu baseline and velocity L2 references (oracle on host cores)")
-        cpu, refs = oracle_leg([HEADLINE] + [f for f in forms if f != REFINED])
+        cpu, refs = oracle_leg([HEADLINE] + [f for f in forms if f not in REFINED_FORMS])
         log(f"[bench]   {cpu}")
-        if REFINED in forms:
-            forms[REFINED]["velocity_l2_vs_oracle"] = refined_l2()
-            log(f"[bench]   velocity L2 {REFINED}: {forms[REFINED]['velocity_l2_vs_oracle']}")
-        for key in [HEADLINE] + [f for f in forms if f != REFINED]:
+        for key in REFINED_FORMS:
+            if key in forms:
+                forms[key]["velocity_l2_vs_oracle"] = refined_l2(key)
+                log(f"[bench]   velocity L2 {key}: {forms[key]['velocity_l2_vs_oracle']}")
+        for key in [HEADLINE] + [f for f in forms if f not in REFINED_FORMS]:
             l2[key] = gpu_l2(key, refs)
             log(f"[bench]   velocity L2 {key}: {l2[key]}")
             if key in forms:

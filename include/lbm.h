@@ -376,7 +376,8 @@ int lbm_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, void *stre
  * second half of the last coarse step's packets.
  *
  * lbm_refine_work_bytes: bytes of the work buffer for a coarse domain (FP32
- * planes [2][2][q][nz][nx]).  LBM_EINVAL for NULL or a bad stencil. */
+ * planes [2][q][nz][nx]: the fine packets' running sums, one plane per
+ * interface side).  LBM_EINVAL for NULL or a bad stencil. */
 int lbm_refine_work_bytes(const lbm_domain *coarse, int stencil, size_t *bytes);
 
 /* Advance the coarse lattice n >= 0 steps and each fine lattice 2n steps.

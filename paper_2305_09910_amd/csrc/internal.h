@@ -116,14 +116,11 @@ hipError_t launch_totals(const LatticeArgs &a, const SparseArgs &sp, int q, int 
                          double *final_out, hipStream_t s);
 hipError_t launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
-// 2:1 refinement exchange (lbm_refine.hip); plane buffers [q][nz_c][nx_c] FP32
-hipError_t launch_refine_record(const LatticeArgs &c, int q, int st, int yc, int dy, float *cout, hipStream_t s);
-hipError_t launch_refine_add(const LatticeArgs &f, int q, int st, int yf, int dy, int nxc, int nzc, int first,
-                             float *acc, hipStream_t s);
-hipError_t launch_refine_fill_fine(const LatticeArgs &f, int q, int st, int yf, int dy, int nxc, int nzc,
-                                   const float *cout, hipStream_t s);
-hipError_t launch_refine_fill_coarse(const LatticeArgs &c, int q, int st, int yc, int dy, const float *acc,
-                                     hipStream_t s);
+// 2:1 refinement exchange after a fine step (lbm_refine.hip): coarse lattice c
+// (storage sc, interface row yc), fine lattice f (storage sf, interface row
+// yf), dy = +1 for f above c; acc [q][nz_c][nx_c] FP32
+hipError_t launch_refine_exchange(const LatticeArgs &c, int sc, int yc, const LatticeArgs &f, int q, int sf, int yf,
+                                  int dy, int last, float *acc, hipStream_t s);
 // operand table of the closure network (63 x 64 words) from its parameters
 hipError_t launch_build_mlp_table(const float *params, uint32_t *table, hipStream_t s);
 

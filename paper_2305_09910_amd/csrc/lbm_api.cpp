@@ -655,7 +655,7 @@ int lbm_refine_work_bytes(const lbm_domain *d, int stencil, size_t *bytes)
     if (!d || !bytes) return fail(nullptr, LBM_EINVAL, "refine_work_bytes: NULL pointer");
     if (stencil != 19 && stencil != 27) return fail(nullptr, LBM_EINVAL, "stencil must be 19 or 27, got %d", stencil);
     if (d->nx < 1 || d->nz < 1) return fail(nullptr, LBM_EINVAL, "domain sizes must be >= 1");
-    *bytes = 4 * refine_plane_floats(stencil, d->nx, d->nz) * sizeof(float);
+    *bytes = 2 * refine_plane_floats(stencil, d->nx, d->nz) * sizeof(float);
     return LBM_OK;
 }
 
@@ -691,36 +691,26 @@ static int refine_check(lbm_ctx *root, int kc, const lbm_ctx *c, int kf, const l
     return LBM_OK;
 }
 
-// Advance node k one step: its own step, then per child the recorded packets,
-// two child steps (recursively) each followed by add and fill, and finally
-// the node's interface rows from the sums.
+// Advance node k one step: its own step, then per child two child steps
+// (recursively), each followed by the exchange across their interface; the
+// second exchange also fills node k's interface row toward that child.
 static int refine_advance(const lbm_refine_node *nodes, int k)
 {
     lbm_ctx *c = nodes[k].ctx;
     int rc = step_once(c);
     if (rc) return rc;
     const size_t plane = refine_plane_floats(c->q, c->a.nx, c->a.nz);
-    float *buf = (float *)nodes[k].work_dev;
     const int child[2] = {nodes[k].fine_lo, nodes[k].fine_hi};
     for (int side = 0; side < 2; ++side) {
         if (child[side] < 0) continue;
         lbm_ctx *f = nodes[child[side]].ctx;
         const int dy = side ? 1 : -1, yc = side ? c->a.ny - 1 : 0, yf = side ? 0 : f->a.ny - 1;
-        float *cout = buf + (size_t)(2 * side) * plane, *acc = cout + plane;
-        HIPCHECK(c, launch_refine_record(c->a, c->q, c->st, yc, dy, cout, c->stream), "refine record");
+        float *acc = (float *)nodes[k].work_dev + (size_t)side * plane;
         for (int sub = 0; sub < 2; ++sub) {
             if ((rc = refine_advance(nodes, child[side]))) return rc;
-            HIPCHECK(c, launch_refine_add(f->a, f->q, f->st, yf, dy, c->a.nx, c->a.nz, sub == 0, acc, c->stream),
-                     "refine add");
-            HIPCHECK(c, launch_refine_fill_fine(f->a, f->q, f->st, yf, dy, c->a.nx, c->a.nz, cout, c->stream),
-                     "refine fill fine");
+            HIPCHECK(c, launch_refine_exchange(c->a, c->st, yc, f->a, c->q, f->st, yf, dy, sub, acc, c->stream),
+                     "refine exchange");
         }
-    }
-    for (int side = 0; side < 2; ++side) {
-        if (child[side] < 0) continue;
-        const int dy = side ? 1 : -1, yc = side ? c->a.ny - 1 : 0;
-        HIPCHECK(c, launch_refine_fill_coarse(c->a, c->q, c->st, yc, dy, buf + (size_t)(2 * side + 1) * plane, c->stream),
-                 "refine fill coarse");
     }
     return LBM_OK;
 }
@@ -750,7 +740,7 @@ int lbm_refine_tree_step(const lbm_refine_node *nodes, int32_t count, int64_t n)
             if (rc) return rc;
         }
         if (child[0] >= 0 || child[1] >= 0) {
-            const size_t need = 4 * refine_plane_floats(c->q, c->a.nx, c->a.nz) * sizeof(float);
+            const size_t need = 2 * refine_plane_floats(c->q, c->a.nx, c->a.nz) * sizeof(float);
             if (!nodes[k].work_dev || ((uintptr_t)nodes[k].work_dev & 3) != 0)
                 return fail(root, LBM_EINVAL, "refine: node %d needs a 4-byte aligned work buffer", k);
             if (nodes[k].work_bytes < need)

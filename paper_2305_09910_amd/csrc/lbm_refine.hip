@@ -15,24 +15,28 @@
 //
 // Populations are stored as deviations f_i - w_i; w_i = w_opposite(i), so the
 // exchange works on deviations directly (a copy is exact, and an average of
-// deviations is the deviation of the average).  Per coarse step:
-//   record:      cout[i](X) = f_opp(i)(X) of the coarse interface row, c_iy = dy
-//                (the packet coarse cell X sent across toward the fine level);
-//   twice:       fine step; add: acc[i](Y) (+)= 1/8 sum of f_opp(i)(x_f) over
-//                the four fine interface cells whose target x_f + c_i lies in
-//                coarse cell Y, c_iy = -dy; fill fine: f_j(x_f) = cout[j](X)
-//                for the coarse cell X containing the source point x_f - c_j,
-//                c_jy = dy;
-//   fill coarse: f_i(Y) = acc[i](Y) in the coarse interface row, c_iy = -dy.
-// dy is +1 for a fine lattice above the coarse one, -1 below.  The plane
-// buffers cout and acc are [q][nz_c][nx_c] FP32; only the directions named
-// above are used.
+// deviations is the deviation of the average).  dy is +1 for a fine lattice
+// above the coarse one, -1 below.  For each crossing direction i toward the
+// coarse level (c_iy = -dy) and j = opp(i), per coarse step:
+//   - the packet coarse interface cell X sent toward the fine level along j
+//     is f*_j(X), which the coarse step left in X's own slot i; it stays
+//     there until the coarse interface row is filled at the end;
+//   - after each of the two fine steps: the fine interface cells x_f with
+//     x_f + c_i in X (four of them) sent f*_i(x_f), now in their own slot j;
+//     1/8 of their sum is added to acc_i(X), and slot j of the same cells
+//     takes X's packet f*_j(X) (the source point x_f - c_j = x_f + c_i of
+//     its link lies in X);
+//   - after the second fine step, slot i of X takes acc_i(X).
+// So one thread per coarse interface cell does all of it with no other
+// thread touching its cells' slots, and the exchange is two launches per
+// coarse step and fine level: k_refine_exchange after the first fine step
+// (first: acc = sum) and after the second (last: X's slot i = acc + sum).
+// acc is [q][nz_c][nx_c] FP32; only the directions i with c_iy = -dy are used.
 //
-// Bytes per launch (FP32): record and fill coarse 4 (q_y) n_c * (4 + 4), add
-// 4 (q_y) n_c * (4 * 4 + 4), fill fine 4 (q_y) 4 n_c * (4 + 4) (the plane
-// buffer is read from cache), with q_y = 5 (D3Q19) or 9 (D3Q27) directions
-// and n_c = nx_c nz_c coarse interface cells: a few MB per coarse step at
-// the sizes of interest, small beside the levels' own steps.
+// Bytes per launch (FP32 storage): per coarse interface cell and crossing
+// direction (5 of D3Q19, 9 of D3Q27) 4 fine slots read and written (32 B),
+// the coarse slot read (4 B), and acc written (first, 4 B) or read with the
+// coarse slot written (last, 8 B).
 #include "lattice.h"
 
 namespace lbm {
@@ -41,37 +45,24 @@ constexpr int kRefineThreads = 256;
 
 __device__ inline int wrap_int(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// record the packets coarse interface row yc sent across
-template <int Q, int ST>
-__global__ void __launch_bounds__(kRefineThreads) k_refine_record(LatticeArgs a, int yc, int dy, float *cout)
-{
-    using S = Store<ST>;
-    const typename S::T *A = (const typename S::T *)a.pdf;
-    const int x = blockIdx.x * kRefineThreads + threadIdx.x, z = blockIdx.y;
-    if (x >= a.nx) return;
-    const Geom g = make_geom(a, x, yc, z);
-    const size_t plane = (size_t)a.nx * a.nz, k = (size_t)z * a.nx + x;
-    for_dirs<1, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        if (cdir(i, 1) == dy) cout[i * plane + k] = S::ld(A + pidx<Q>(a, opp(i), g.row, x));
-    });
-}
-
-// fine packets sent across: a gather per coarse cell (four fine cells per
-// direction), so no two threads write one sum
-template <int Q, int ST>
+// the exchange after a fine step (see above): one thread per coarse interface cell (X, Z)
+template <int Q, int SC, int SF>
 __global__ void __launch_bounds__(kRefineThreads)
-    k_refine_add(LatticeArgs f, int yf, int dy, int nxc, int nzc, int first, float *acc)
+    k_refine_exchange(LatticeArgs c, int yc, LatticeArgs f, int yf, int dy, int last, float *acc)
 {
-    using S = Store<ST>;
-    const typename S::T *A = (const typename S::T *)f.pdf;
+    using C = Store<SC>;
+    using F = Store<SF>;
+    typename C::T *Ac = (typename C::T *)c.pdf;
+    typename F::T *Af = (typename F::T *)f.pdf;
     const int X = blockIdx.x * kRefineThreads + threadIdx.x, Z = blockIdx.y;
-    if (X >= nxc) return;
-    const size_t plane = (size_t)nxc * nzc, k = (size_t)Z * nxc + X;
+    if (X >= c.nx) return;
+    const Geom gc = make_geom(c, X, yc, Z);
+    const size_t plane = (size_t)c.nx * c.nz, k = (size_t)Z * c.nx + X;
     for_dirs<1, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+        constexpr int i = decltype(I)::value, j = opp(i);
         if (cdir(i, 1) != -dy) return;
-        // fine cells x_f with x_f + c_i in {2X, 2X + 1} (and the same in z)
+        const uint64_t ci = pidx<Q>(c, i, gc.row, X);
+        const auto packet = F::cvt(C::ld(Ac + ci));
         float s = 0.f;
 #pragma unroll
         for (int bz = 0; bz < 2; ++bz) {
@@ -80,82 +71,31 @@ __global__ void __launch_bounds__(kRefineThreads)
 #pragma unroll
             for (int bx = 0; bx < 2; ++bx) {
                 const int xf = wrap_int(2 * X + bx - cdir(i, 0), f.nx);
-                s += S::ld(A + pidx<Q>(f, opp(i), g.row, xf));
+                typename F::T *p = Af + pidx<Q>(f, j, g.row, xf);
+                s += F::ld(p);
+                *p = packet;
             }
         }
         const float v = 0.125f * s;
-        acc[i * plane + k] = first ? v : acc[i * plane + k] + v;
+        if (last)
+            Ac[ci] = C::cvt(acc[i * plane + k] + v);
+        else
+            acc[i * plane + k] = v;
     });
 }
 
-// the coarse packets enter the fine interface row
-template <int Q, int ST>
-__global__ void __launch_bounds__(kRefineThreads)
-    k_refine_fill_fine(LatticeArgs f, int yf, int dy, int nxc, int nzc, const float *cout)
+hipError_t launch_refine_exchange(const LatticeArgs &c, int sc, int yc, const LatticeArgs &f, int q, int sf, int yf,
+                                  int dy, int last, float *acc, hipStream_t s)
 {
-    using S = Store<ST>;
-    typename S::T *A = (typename S::T *)f.pdf;
-    const int x = blockIdx.x * kRefineThreads + threadIdx.x, z = blockIdx.y;
-    if (x >= f.nx) return;
-    const Geom g = make_geom(f, x, yf, z);
-    const size_t plane = (size_t)nxc * nzc;
-    for_dirs<1, Q>([&](auto J) {
-        constexpr int j = decltype(J)::value;
-        if (cdir(j, 1) != dy) return;
-        const int px = wrap_int(x - cdir(j, 0), f.nx) >> 1, pz = wrap_int(z - cdir(j, 2), f.nz) >> 1;
-        A[pidx<Q>(f, j, g.row, x)] = S::cvt(cout[j * plane + (size_t)pz * nxc + px]);
-    });
-}
-
-// the summed fine packets enter the coarse interface row
-template <int Q, int ST>
-__global__ void __launch_bounds__(kRefineThreads) k_refine_fill_coarse(LatticeArgs a, int yc, int dy, const float *acc)
-{
-    using S = Store<ST>;
-    typename S::T *A = (typename S::T *)a.pdf;
-    const int x = blockIdx.x * kRefineThreads + threadIdx.x, z = blockIdx.y;
-    if (x >= a.nx) return;
-    const Geom g = make_geom(a, x, yc, z);
-    const size_t plane = (size_t)a.nx * a.nz, k = (size_t)z * a.nx + x;
-    for_dirs<1, Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        if (cdir(i, 1) == -dy) A[pidx<Q>(a, i, g.row, x)] = S::cvt(acc[i * plane + k]);
-    });
-}
-
-static dim3 plane_grid(int nx, int nz) { return dim3((unsigned)((nx + kRefineThreads - 1) / kRefineThreads), (unsigned)nz, 1); }
-
-hipError_t launch_refine_record(const LatticeArgs &c, int q, int st, int yc, int dy, float *cout, hipStream_t s)
-{
-    return dispatch(q, st, [&](auto Q, auto ST) {
-        k_refine_record<Q.value, ST.value><<<plane_grid(c.nx, c.nz), kRefineThreads, 0, s>>>(c, yc, dy, cout);
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_refine_add(const LatticeArgs &f, int q, int st, int yf, int dy, int nxc, int nzc, int first,
-                             float *acc, hipStream_t s)
-{
-    return dispatch(q, st, [&](auto Q, auto ST) {
-        k_refine_add<Q.value, ST.value><<<plane_grid(nxc, nzc), kRefineThreads, 0, s>>>(f, yf, dy, nxc, nzc, first, acc);
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_refine_fill_fine(const LatticeArgs &f, int q, int st, int yf, int dy, int nxc, int nzc,
-                                   const float *cout, hipStream_t s)
-{
-    return dispatch(q, st, [&](auto Q, auto ST) {
-        k_refine_fill_fine<Q.value, ST.value><<<plane_grid(f.nx, f.nz), kRefineThreads, 0, s>>>(f, yf, dy, nxc, nzc, cout);
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_refine_fill_coarse(const LatticeArgs &c, int q, int st, int yc, int dy, const float *acc, hipStream_t s)
-{
-    return dispatch(q, st, [&](auto Q, auto ST) {
-        k_refine_fill_coarse<Q.value, ST.value><<<plane_grid(c.nx, c.nz), kRefineThreads, 0, s>>>(c, yc, dy, acc);
-        return hipGetLastError();
+    const dim3 grid((unsigned)((c.nx + kRefineThreads - 1) / kRefineThreads), (unsigned)c.nz, 1);
+    return dispatch(q, sf, [&](auto Q, auto SF) {
+        auto go = [&](auto SC) {
+            k_refine_exchange<Q.value, SC.value, SF.value><<<grid, kRefineThreads, 0, s>>>(c, yc, f, yf, dy, last, acc);
+            return hipGetLastError();
+        };
+        if (sc == ST_F32) return go(std::integral_constant<int, ST_F32>{});
+        if (sc == ST_F16) return go(std::integral_constant<int, ST_F16>{});
+        return go(std::integral_constant<int, ST_BF16>{});
     });
 }
 

@@ -233,13 +233,13 @@ def test_create_rejects_before_device(L, case):
 
 
 def test_refine_work_bytes(L):
-    """Two FP32 planes (recorded coarse packets, summed fine packets) of q x
-    nz x nx per interface side, two sides."""
+    """One FP32 plane of q x nz x nx (the summed fine packets) per interface
+    side, two sides."""
     out = ctypes.c_size_t(0)
     d = lbm.make_domain((24, 8, 10))
     for q in (19, 27):
         assert L.lbm_refine_work_bytes(ctypes.byref(d), q, ctypes.byref(out)) == lbm.LBM_OK
-        assert out.value == 4 * q * 24 * 10 * 4
+        assert out.value == 2 * q * 24 * 10 * 4
     assert L.lbm_refine_work_bytes(ctypes.byref(d), 15, ctypes.byref(out)) == lbm.LBM_EINVAL
     assert L.lbm_refine_work_bytes(None, 19, ctypes.byref(out)) == lbm.LBM_EINVAL
     assert L.lbm_refine_step(None, None, None, None, 0, 1) == lbm.LBM_EINVAL
