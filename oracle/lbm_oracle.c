@@ -1479,8 +1479,10 @@ void orc_strain(int cx, int cy, int cz, const int *periodic, const double *u, do
  *   tau_sgs = <u u> - <u><u>,  nu_t* = max(0, -dev(tau_sgs):S / (2 S:S + eps)),
  * and the six features of the flux the coarse lattice would carry,
  * P = -(2/3)(tau + dtau*) S.  x[nc][6], t[nc].
- * Parity unpinned beyond its parts (strain, features) and the closed form of
- * a pure-shear sample (tests).
+ * Pinned by the closed form of a box-filtered linear fine field (subgrid
+ * stress 1.25 G G^T, strain 4 sym G, target and features), which a dropped
+ * dev, a wrong contraction weight, sign, factor or clip fails, and by a
+ * pure-shear sample (tests).
  */
 void orc_closure_dataset(int cx, int cy, int cz, const int *periodic, const double *filt, double tau, double cs,
                          double eps, double *x, double *t)

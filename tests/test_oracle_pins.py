@@ -903,6 +903,55 @@ def test_closure_dataset_features_pure_shear():
         assert abs(tt * tt - tau * tt - 4.5 * math.sqrt(2) * cs * cs * Q) < 1e-16
 
 
+def test_closure_dataset_linear_field_closed_form():
+    """The whole dataset pipeline (box filter, subgrid stress, strain, target,
+    features) on a fine linear field u = G x + u0, against the closed form.
+    Over a 4-cell box each coordinate has variance (0+1+4+9)/4 - 1.5^2 = 1.25,
+    so tau_sgs = <u u> - <u><u> = 1.25 G G^T exactly; the filtered velocity
+    has the gradient 4 G per coarse cell, so S = 4 sym(G) (central
+    differences are exact on it).  Then nu_t* = max(0, -dev(tau_sgs):S /
+    (2 S:S)), dtau* = 3 nu_t*, and the features are those of P = -(2/3)(tau
+    + dtau*) S: trace, |dev P| and cbrt(det dev P) from its eigenvalues, and
+    the Smagorinsky excess as the root of the Hou quadratic with Q = |P|.  G
+    has a trace, so dropping dev or taking |P| for |dev P| fails; -G gives
+    the opposite sign of dev(tau_sgs):S and so a clipped target of 0."""
+    n = 20
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    X = np.stack([x, y, z]).astype(float)
+    G0 = 1e-3 * np.array([[-1.0, 0.3, 0.1], [0.2, -2.0, 0.4], [-0.1, 0.25, -3.0]])
+    tau, cs = 0.52, 0.1
+    for sign in (1.0, -1.0):
+        G = sign * G0
+        u = np.einsum("ab,bzyx->azyx", G, X) + np.array([0.02, -0.01, 0.005])[:, None, None, None]
+        filt = oracle.box_filter4(np.ones((n, n, n)), u)
+        x6, t = oracle.closure_dataset(filt, periodic=(0, 0, 0), tau=tau, cs=cs)
+        S = 4 * 0.5 * (G + G.T)
+        tsgs = 1.25 * G @ G.T
+        dev = tsgs - np.trace(tsgs) / 3 * np.eye(3)
+        nu = max(0.0, -np.sum(dev * S) / (2 * np.sum(S * S)))
+        if sign > 0:
+            assert nu > 0  # a case that is not clipped
+        else:
+            assert nu == 0.0
+        P = -(2 / 3) * (tau + 3 * nu) * S
+        Pd = P - np.trace(P) / 3 * np.eye(3)
+        ev = np.linalg.eigvalsh(Pd)
+        c = np.arange(5)
+        inner = ((c[:, None, None] > 0) & (c[:, None, None] < 4) & (c[None, :, None] > 0) & (c[None, :, None] < 4)
+                 & (c[None, None, :] > 0) & (c[None, None, :] < 4)).reshape(-1)
+        assert inner.sum() == 27
+        for r in np.nonzero(inner)[0]:
+            assert abs(t[r] - 3 * nu) <= 1e-9 * 3 * abs(G0).max() + 1e-18
+            f6 = x6[r]
+            assert abs(f6[0] - np.trace(P)) <= 1e-9 * abs(np.trace(P))
+            assert abs(f6[1] - np.sqrt((ev ** 2).sum())) <= 1e-9 * f6[1]
+            assert abs(f6[2] - np.cbrt(np.prod(ev))) <= 1e-8 * abs(f6[2])
+            assert abs(f6[3]) < 1e-14 and f6[5] == tau
+            Q = np.linalg.norm(P)
+            tt = tau + f6[4]
+            assert abs(tt * tt - tau * tt - 4.5 * math.sqrt(2) * cs * cs * Q) < 1e-15
+
+
 def _corner_case(bc, u_bc, q=19, shape=(3, 3, 2), seed=41):
     """One step of an oracle lattice from seeded non-equilibrium populations;
     returns the new state and the pre-step state."""
