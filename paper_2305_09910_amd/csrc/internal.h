@@ -62,6 +62,10 @@ struct LatticeArgs {
 
 // cell count of a lattice
 __host__ __device__ inline uint64_t cells(const LatticeArgs &a) { return (uint64_t)a.nrows * (uint32_t)a.nx; }
+// After the n mask words: per cell row, one word per run of 64 cells along x,
+// nonzero when a cell of the run has a nonzero mask word (a solid cell or a
+// link cut by one), so that wavefronts far from solids skip the mask words.
+__host__ __device__ inline uint32_t mask_runs(int nx) { return ((uint32_t)nx + 63u) >> 6; }
 
 // Sparse addressing (the AA pattern over the fluid cells only), passed as an
 // argument of its own to the kernels that use it: the dense step kernels keep

@@ -11,7 +11,8 @@
 //   velocities   (HRR only) two velocity fields of 3 * n FP32, the input and
 //                output of the finite-difference gradient; with the
 //                populations they form the state that checkpoints copy
-//   mask         n uint32 words (only with use_flags)
+//   mask         n uint32 words, then one word per cell row and run of 64
+//                cells along x (only with use_flags)
 //   sparse       (sparse addressing only) fluid map (n int32), fluid cells'
 //                linear indices (nf uint32) and neighbour table ((q-1) * nf uint32)
 //   totals       partial sums (1024 blocks x 5 doubles) and the final 5
@@ -132,7 +133,7 @@ static int make_layout(const lbm_domain *d, int q, Layout *L, lbm_ctx *c, int64_
     off += 2 * L->uvel_bytes;
     L->state_bytes = d->collision == LBM_COLL_HRR ? off : L->pdf_bytes;
     L->mask = off;
-    if (d->use_flags) off += al256(4 * n);
+    if (d->use_flags) off += al256(4 * (n + (uint64_t)d->ny * (uint64_t)d->nz * mask_runs(d->nx)));
     L->fmap = L->fcell = L->nbt = off;
     if (sp) {
         off += al256(4 * n);

@@ -83,7 +83,9 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES)
     const Geom g = make_geom(a, active ? x : 0, active ? y : 0, z);
     uint32_t m = 0;
     if constexpr (MASK) {
-        m = active ? a.mask[cidx(a, g)] : 0u;
+        // the cell's mask word only where its run of 64 cells touches a solid
+        if (active && a.mask[cells(a) + (uint64_t)g.frow * mask_runs(a.nx) + ((uint32_t)x >> 6)])
+            m = a.mask[cidx(a, g)];
         if (m & SELF_SOLID) {
             if constexpr (kKeepSolid) {
                 if (odd) {
@@ -253,6 +255,19 @@ __global__ void __launch_bounds__(LBM_LB_THREADS) k_build_mask(LatticeArgs a, co
         if (!face_cut(g, dx, dy, dz) && flags[nbr(a, g, dx, dy, dz)]) m |= 1u << i;
     }
     mask[cidx(a, g)] = m;
+}
+
+// the run words after the mask (one thread per row and run of 64 cells)
+__global__ void __launch_bounds__(256) k_build_mask_runs(LatticeArgs a, uint32_t *mask)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nr = mask_runs(a.nx);
+    if (t >= (uint64_t)a.nrows * nr) return;
+    const uint64_t row = t / nr;
+    const int x0 = (int)(t - row * nr) * 64, x1 = min(x0 + 64, a.nx);
+    uint32_t any = 0;
+    for (int x = x0; x < x1; ++x) any |= mask[row * (uint32_t)a.nx + (uint32_t)x];
+    mask[cells(a) + t] = any != 0u;
 }
 
 template <int Q, int ST>
@@ -484,6 +499,8 @@ hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, 
         k_build_mask<19><<<L.grid, L.block, 0, s>>>(a, flags, mask);
     else
         k_build_mask<27><<<L.grid, L.block, 0, s>>>(a, flags, mask);
+    const uint64_t nruns = (uint64_t)a.nrows * mask_runs(a.nx);
+    k_build_mask_runs<<<(unsigned)((nruns + 255) / 256), 256, 0, s>>>(a, mask);
     return hipGetLastError();
 }
 
