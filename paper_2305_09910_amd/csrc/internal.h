@@ -15,6 +15,10 @@ enum { COLL_TRT = 0, COLL_MRT = 1, COLL_HRR = 2 };
 // masked AA kernel to rewrite solid cells' own slots on odd steps (whole
 // cache lines along solid surfaces; worth it when solids are sparse)
 constexpr int SC_SOLID_ODD = 2;
+// SC_MASK_RUNS: the masked AA kernel reads a cell's mask word only where the
+// run word of its 64 cells is nonzero (sparse solids; with dense solids
+// nearly every run is nonzero and the extra dependent load costs time)
+constexpr int SC_MASK_RUNS = 4;
 enum { BC_PERIODIC = 0, BC_NOSLIP = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
 
 // Bit 31 of a cell's mask word marks the cell itself as solid; bit i
@@ -94,7 +98,7 @@ Launch lattice_launch(const LatticeArgs &a);
 
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_build_mask(const LatticeArgs &a, int q, const uint8_t *flags, uint32_t *mask, hipStream_t s);
-// odd: bit 0 the step parity, optionally | SC_SOLID_ODD
+// odd: bit 0 the step parity, optionally | SC_SOLID_ODD | SC_MASK_RUNS
 hipError_t launch_step(const LatticeArgs &a, const HrrArgs &h, int q, int st, int cl, int coll, int odd, hipStream_t s);
 // Esoteric Twist step (lbm_et.hip)
 hipError_t launch_step_et(const LatticeArgs &a, int q, int st, int cl, int coll, int odd, hipStream_t s);

@@ -37,7 +37,8 @@ namespace lbm {
 // the fused stream-collide kernel
 // ---------------------------------------------------------------------------
 // flags: bit 0 the step parity (1: odd step); bit 1 (SC_SOLID_ODD): on the
-// odd step solid lanes rewrite their own slots unchanged (see below)
+// odd step solid lanes rewrite their own slots unchanged (see below); bit 2
+// (SC_MASK_RUNS): mask words only in runs that touch a solid
 template <int Q, int ST, int CL, bool MASK, int COLL>
 __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES)
     k_stream_collide(LatticeArgs a, int flags, [[maybe_unused]] HrrArgs h)
@@ -83,8 +84,9 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES)
     const Geom g = make_geom(a, active ? x : 0, active ? y : 0, z);
     uint32_t m = 0;
     if constexpr (MASK) {
-        // the cell's mask word only where its run of 64 cells touches a solid
-        if (active && a.mask[cells(a) + (uint64_t)g.frow * mask_runs(a.nx) + ((uint32_t)x >> 6)])
+        // with SC_MASK_RUNS the cell's mask word only where its run of 64
+        // cells touches a solid
+        if (active && (!(flags & SC_MASK_RUNS) || a.mask[cells(a) + (uint64_t)g.frow * mask_runs(a.nx) + ((uint32_t)x >> 6)]))
             m = a.mask[cidx(a, g)];
         if (m & SELF_SOLID) {
             if constexpr (kKeepSolid) {
