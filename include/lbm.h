@@ -402,7 +402,8 @@ int lbm_refine_step(lbm_ctx *coarse, lbm_ctx *fine_lo, lbm_ctx *fine_hi, void *w
  * interface exactly where it meets another level (so a child has no child on
  * its parent's side).  work_dev / work_bytes: the node's work buffer as for
  * lbm_refine_step, needed by nodes with a child (distinct buffers; ignored
- * otherwise).  The node array is read during the call only. */
+ * otherwise; LBM_EINVAL if two of them overlap).  The node array is read
+ * during the call only. */
 typedef struct lbm_refine_node {
     lbm_ctx *ctx;
     int32_t fine_lo, fine_hi;

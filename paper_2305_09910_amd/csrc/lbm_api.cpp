@@ -24,6 +24,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -753,6 +754,19 @@ int lbm_refine_tree_step(const lbm_refine_node *nodes, int32_t count, int64_t n)
     }
     for (int k = 1; k < count; ++k)
         if (parents[k] != 1) return fail(root, LBM_EINVAL, "refine: node %d has %d parents", k, parents[k]);
+    // a parent's sums live from its child's first substep to the second, across
+    // the child's own exchanges: the work buffers must not overlap
+    std::vector<std::pair<uintptr_t, int>> ws;
+    for (int k = 0; k < count; ++k)
+        if (nodes[k].fine_lo >= 0 || nodes[k].fine_hi >= 0) ws.push_back({(uintptr_t)nodes[k].work_dev, k});
+    std::sort(ws.begin(), ws.end());
+    for (size_t j = 1; j < ws.size(); ++j) {
+        const lbm_ctx *c = nodes[ws[j - 1].second].ctx;
+        const uintptr_t end = ws[j - 1].first + 2 * refine_plane_floats(c->q, c->a.nx, c->a.nz) * sizeof(float);
+        if (ws[j].first < end)
+            return fail(root, LBM_EINVAL, "refine: the work buffers of nodes %d and %d overlap", ws[j - 1].second,
+                        ws[j].second);
+    }
     for (int k = 0; k < count; ++k) {
         const int child[2] = {nodes[k].fine_lo, nodes[k].fine_hi};
         for (int side = 0; side < 2; ++side) {

@@ -6,6 +6,8 @@ walls, a moving lid, a body force); a one-sided chain four levels deep; mass
 over levels (sum of M / 8^depth); the force-driven channel's exact profile
 across four interfaces; and the rejection of malformed trees."""
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -186,3 +188,31 @@ def test_tree_rejects_malformed_trees(case):
     assert e.value.code == lbm.LBM_EINVAL
     print(f"refine tree {case}: {e.value}")
     assert all(g.time == 0 for g, _, _ in gpu)  # nothing ran
+
+
+def test_tree_rejects_overlapping_work_buffers():
+    """A parent's sums live across its child's own exchanges, so two parents
+    sharing a work buffer are rejected before anything runs."""
+    from paper_2305_09910_amd import lbm
+    I = "interface"
+    spec = [((2, 3, 2), 0, (I, "noslip"), 1, None),
+            ((4, 3, 4), 1, (I, I), 2, None),
+            ((8, 3, 8), 2, ("noslip", I), None, None)]
+    gpu, _ = make(spec, 19, 0.6, (0, 0, 0), np.zeros((6, 3)))
+    need = ctypes.c_size_t(0)
+    L = lbm.lib()
+    assert L.lbm_refine_work_bytes(ctypes.byref(gpu[1][0].domain), 19, ctypes.byref(need)) == lbm.LBM_OK
+    work = torch.empty(2 * need.value, dtype=torch.uint8, device="cuda")
+    arr = (lbm.RefineNode * 3)()
+    for k, (lat, lo, hi) in enumerate(gpu):
+        arr[k].ctx = lat._h
+        arr[k].fine_lo = -1 if lo is None else lo
+        arr[k].fine_hi = -1 if hi is None else hi
+    arr[0].work_dev, arr[0].work_bytes = work.data_ptr(), need.value
+    arr[1].work_dev, arr[1].work_bytes = work.data_ptr() + 256, need.value
+    assert L.lbm_refine_tree_step(arr, 3, 1) == lbm.LBM_EINVAL
+    assert b"overlap" in L.lbm_last_error(gpu[0][0]._h)
+    arr[1].work_dev = work.data_ptr() + need.value  # disjoint: runs
+    assert L.lbm_refine_tree_step(arr, 3, 1) == lbm.LBM_OK
+    torch.cuda.synchronize()
+    assert [g.time for g, _, _ in gpu] == [1, 2, 4]
