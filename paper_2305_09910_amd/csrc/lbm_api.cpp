@@ -719,7 +719,7 @@ static int refine_advance(const lbm_refine_node *nodes, int k)
     return LBM_OK;
 }
 
-int lbm_refine_tree_step(const lbm_refine_node *nodes, int32_t count, int64_t n)
+static int refine_tree_step(const lbm_refine_node *nodes, int32_t count, int64_t n)
 {
     if (!nodes || count < 1 || count > 4096) return fail(nullptr, LBM_EINVAL, "refine: need 1 to 4096 nodes");
     for (int k = 0; k < count; ++k)
@@ -783,6 +783,15 @@ int lbm_refine_tree_step(const lbm_refine_node *nodes, int32_t count, int64_t n)
         if (rc) return rc;
     }
     return LBM_OK;
+}
+
+int lbm_refine_tree_step(const lbm_refine_node *nodes, int32_t count, int64_t n)
+{
+    try {  // the validation's small host arrays
+        return refine_tree_step(nodes, count, n);
+    } catch (const std::bad_alloc &) {
+        return fail(nodes && count > 0 ? nodes[0].ctx : nullptr, LBM_ENOMEM, "refine: out of host memory");
+    }
 }
 
 int lbm_refine_step(lbm_ctx *c, lbm_ctx *lo, lbm_ctx *hi, void *work_dev, size_t work_bytes, int64_t n)
