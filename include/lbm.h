@@ -416,8 +416,9 @@ typedef struct lbm_refine_node {
  * advances two steps (recursively, each followed by the exchange of
  * lbm_refine_step), then the node's interface rows take the summed packets.
  * 1 <= count <= 4096.  Errors as for lbm_refine_step, reported on nodes[0]
- * (on the thread's global error text for a NULL array or context); a
- * failed launch leaves every level part way through a step.
+ * (on the thread's global error text for a NULL array or context), and
+ * LBM_ENOMEM when the host memory for the validation runs out; a failed
+ * launch leaves every level part way through a step.
  * lbm_refine_step(c, lo, hi, ...) is this call on the nodes {c, lo, hi}. */
 int lbm_refine_tree_step(const lbm_refine_node *nodes, int32_t count, int64_t n);
 
