@@ -12,7 +12,7 @@ enum { CL_NONE = 0, CL_SMAG = 1, CL_MLP = 2 };
 enum { COLL_TRT = 0, COLL_MRT = 1, COLL_HRR = 2 };
 
 // launch_step's `odd` argument: bit 0 the step parity; SC_SOLID_ODD asks the
-// masked AA kernel to rewrite solid cells' own slots on odd steps (whole
+// masked AA kernel to fill solid cells' own slots on odd steps (whole
 // cache lines along solid surfaces; worth it when solids are sparse)
 constexpr int SC_SOLID_ODD = 2;
 // SC_MASK_RUNS: the masked AA kernel reads a cell's mask word only where the

@@ -335,9 +335,9 @@ int lbm_create(const lbm_domain *d, int stencil, const uint8_t *flags, double ta
     a.fallbacks = c->fallbacks;
 
     c->nfluid = nf;
-    // Solid lanes rewrite their own slots on odd steps where solids are
-    // sparse: whole lines along solid surfaces for the solid cells' extra
-    // bytes (measured: -2.1% per step at 10% solid, +18% at 70%).
+    // Solid lanes fill their own slots on odd steps where solids are sparse:
+    // whole lines along solid surfaces for the solid cells' extra bytes
+    // (measured: about -2% per step at 10% solid, +18% at 70%).
     c->sc_flags = (c->mask && !sp && !a.et && (double)(ncell - (uint64_t)nf) <= 0.2 * (double)ncell)
                       ? SC_SOLID_ODD | SC_MASK_RUNS
                       : 0;

@@ -37,7 +37,8 @@ namespace lbm {
 // the fused stream-collide kernel
 // ---------------------------------------------------------------------------
 // flags: bit 0 the step parity (1: odd step); bit 1 (SC_SOLID_ODD): on the
-// odd step solid lanes rewrite their own slots unchanged (see below); bit 2
+// odd step solid lanes write zero deviations into their own slots (see
+// below); bit 2
 // (SC_MASK_RUNS): mask words only in runs that touch a solid
 template <int Q, int ST, int CL, bool MASK, int COLL>
 __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES)
@@ -74,11 +75,13 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES)
     // 384^3 obstacle flow.  On the odd step no fluid cell reads or writes a
     // solid cell's slots either (links into a solid are cut, and cut links
     // use the fluid cell's own slots), so with SC_SOLID_ODD a solid lane
-    // rewrites its own slots unchanged on the odd step too, filling the holes
-    // that solid cells leave in the lines its row's neighbours write.  That
-    // costs the solid cells' bytes: it pays on sparse solids (384^3 obstacle
-    // flow, 10% solid: odd step -2.9%) and not on dense ones (70%-solid porous
-    // medium: +41%), so the host sets the flag by the solid fraction.
+    // writes zero deviations into its own slots on the odd step, filling the
+    // holes that solid cells leave in the lines its row's neighbours write
+    // (no cell ever reads a solid cell's slots, and the state readers report
+    // solid cells as at rest).  That costs the solid cells' store bytes: it
+    // pays on sparse solids (384^3 obstacle flow, 10% solid: odd step -4%
+    // against no fill) and not on dense ones (70%-solid porous medium), so
+    // the host sets the flag by the solid fraction.
     constexpr bool kKeepSolid = MASK && kUnified && CL != CL_MLP;
     bool keep = false;
     const Geom g = make_geom(a, active ? x : 0, active ? y : 0, z);
@@ -92,14 +95,11 @@ __global__ void __launch_bounds__(LBM_LB_THREADS, LBM_MIN_WAVES)
             if constexpr (kKeepSolid) {
                 if (odd) {
                     if (flags & SC_SOLID_ODD) {
+                        // no cell reads a solid cell's slots (state readers
+                        // report solids as at rest), so zero deviations do
                         typename S::T *A = (typename S::T *)a.pdf;
-                        float v[Q];
 #pragma unroll
-                        for (int i = 0; i < Q; ++i) v[i] = S::ld(A + pidx<Q>(a, i, g.row, g.x));
-                        // (+ 0: a store the compiler cannot drop as a no-op;
-                        // at most turns -0 into +0 in a slot no one reads)
-#pragma unroll
-                        for (int i = 0; i < Q; ++i) S::st(A + pidx<Q>(a, i, g.row, g.x), v[i] + 0.0f);
+                        for (int i = 0; i < Q; ++i) S::st(A + pidx<Q>(a, i, g.row, g.x), 0.0f);
                     }
                     return;
                 }
